@@ -1,0 +1,333 @@
+/*
+ * gift_oracle.c -- plain, slow, FP64 CPU oracle for the GiFt hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the package smoke check and
+ * the benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header, table or helper with the device library; the two meet only through
+ * the seeded inputs drawn by the workload generator.
+ *
+ * What it computes (GiFt, "The Power of Graph Signal Processing for Chip
+ * Placement Acceleration", ICCAD'24):
+ *
+ *   1. netlist -> weighted cell graph with the clique net model (Section 3.2,
+ *      the paragraph after Algorithm 1).  A net of M distinct cells adds weight
+ *      w(M) to every pair of its cells; w(M) = 1/(M-1) (default) or the
+ *      quadratic-wirelength weight 2/M of Section 2.2 (eq. wire_eq).
+ *      Optionally a net of more than T cells is expanded as a star around a new
+ *      virtual node instead (not in the paper; see build()).
+ *   2. adjacency A (weights of parallel edges summed), degrees d_i = sum_j w_ij
+ *      (Section 2.1).
+ *   3. per self-loop weight sigma: the augmented normalised adjacency
+ *      A~_sigma = (D + sigma I)^(-1/2) (A + sigma I) (D + sigma I)^(-1/2)
+ *      (Section 3.2.1, eq. A_formulation).
+ *   4. g' = sum_t alpha_t A~_{sigma_t}^{k_t} g (eq. proposed_filter), each
+ *      power formed by k repeated sparse products (Section 3.2.1, powers of the
+ *      augmented adjacency; complexity paragraph of Section 3.2.2).
+ *
+ * Readings where the paper is silent (each is a stated convention):
+ *   - duplicate pins of one net count once; nets with fewer than two distinct
+ *     cells add nothing; weights of different nets on one pair are summed;
+ *   - the degree excludes the self-loop, which enters only through D + sigma I;
+ *   - t_i = d_i + sigma = 0 (isolated cell, sigma = 0) gives s_i = 0, i.e. the
+ *     row and column vanish;
+ *   - star expansion: virtual node v = N + (number of star nets before e), edge
+ *     weight gamma = M * w(M) between v and every cell of the net (rounded once
+ *     to FP64: M/(M-1) or exactly 2); virtual rows carry the self-loop sigma
+ *     like every row, start at the mean of their cells' signal and are not
+ *     returned;
+ *   - the combine is an FP64 sum in term order.
+ * Summation orders are fixed so the structure, weights and degrees have a
+ * single correct bit pattern: duplicates are summed in ascending net id,
+ * degrees in ascending column, products in ascending column.
+ *
+ * Build with -ffp-contract=off: no fused multiply-adds.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum { ORACLE_OK = 0, ORACLE_EINVAL = 1, ORACLE_ENOMEM = 2 };
+enum { ORACLE_W_INV_M1 = 0, ORACLE_W_TWO_OVER_M = 1 };
+
+typedef struct {
+  int64_t num_cells;   /* N */
+  int64_t num_virtual; /* V */
+  int64_t num_rows;    /* R = N + V */
+  int64_t nnz;         /* off-diagonal entries after merging */
+  int64_t *row_ptr;    /* R + 1 */
+  int32_t *col;        /* nnz */
+  double *w;           /* nnz */
+  double *deg;         /* R */
+  int64_t num_nets;
+  int64_t *ucell_ptr;  /* E + 1: sorted distinct cells of every net */
+  int32_t *ucell;
+  int32_t *virt_net;   /* V: the net each virtual row stands for */
+} oracle_graph;
+
+typedef struct {
+  int32_t row, col, net;
+  double w;
+} triple;
+
+static int cmp_i32(const void *a, const void *b) {
+  int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+  return (x > y) - (x < y);
+}
+
+static int cmp_triple(const void *a, const void *b) {
+  const triple *x = (const triple *)a, *y = (const triple *)b;
+  if (x->row != y->row) return (x->row > y->row) - (x->row < y->row);
+  if (x->col != y->col) return (x->col > y->col) - (x->col < y->col);
+  return (x->net > y->net) - (x->net < y->net);
+}
+
+static double clique_weight(int64_t m, int model) {
+  if (model == ORACLE_W_TWO_OVER_M) return 2.0 / (double)m;
+  return 1.0 / (double)(m - 1);
+}
+
+static double star_weight(int64_t m, int model) {
+  if (model == ORACLE_W_TWO_OVER_M) return 2.0;
+  return (double)m / (double)(m - 1);
+}
+
+void oracle_free(oracle_graph *g) {
+  if (!g) return;
+  free(g->row_ptr);
+  free(g->col);
+  free(g->w);
+  free(g->deg);
+  free(g->ucell_ptr);
+  free(g->ucell);
+  free(g->virt_net);
+  free(g);
+}
+
+/* Steps O1-O4: netlist -> canonical CSR of A and degrees. */
+int oracle_build(int64_t num_cells, int64_t num_nets, int64_t num_pins,
+                 const int64_t *net_ptr, const int32_t *pin_cell,
+                 int weight_model, int64_t star_threshold, oracle_graph **out) {
+  *out = NULL;
+  if (num_cells < 0 || num_nets < 0 || num_pins < 0) return ORACLE_EINVAL;
+  if (weight_model != ORACLE_W_INV_M1 && weight_model != ORACLE_W_TWO_OVER_M)
+    return ORACLE_EINVAL;
+  if (star_threshold < 0) return ORACLE_EINVAL;
+  if (net_ptr[0] != 0 || net_ptr[num_nets] != num_pins) return ORACLE_EINVAL;
+  for (int64_t e = 0; e < num_nets; ++e)
+    if (net_ptr[e + 1] < net_ptr[e]) return ORACLE_EINVAL;
+  for (int64_t p = 0; p < num_pins; ++p)
+    if (pin_cell[p] < 0 || pin_cell[p] >= num_cells) return ORACLE_EINVAL;
+
+  oracle_graph *g = (oracle_graph *)calloc(1, sizeof(oracle_graph));
+  if (!g) return ORACLE_ENOMEM;
+  g->num_cells = num_cells;
+  g->num_nets = num_nets;
+  g->ucell_ptr = (int64_t *)malloc(sizeof(int64_t) * (size_t)(num_nets + 1));
+  g->ucell = (int32_t *)malloc(sizeof(int32_t) * (size_t)(num_pins > 0 ? num_pins : 1));
+  if (!g->ucell_ptr || !g->ucell) { oracle_free(g); return ORACLE_ENOMEM; }
+
+  /* O1: distinct cells of every net, ascending. */
+  int64_t w_at = 0, num_star = 0, z = 0;
+  g->ucell_ptr[0] = 0;
+  for (int64_t e = 0; e < num_nets; ++e) {
+    int64_t a = net_ptr[e], b = net_ptr[e + 1];
+    int32_t *dst = g->ucell + w_at;
+    memcpy(dst, pin_cell + a, sizeof(int32_t) * (size_t)(b - a));
+    qsort(dst, (size_t)(b - a), sizeof(int32_t), cmp_i32);
+    int64_t m = 0;
+    for (int64_t i = 0; i < b - a; ++i)
+      if (m == 0 || dst[i] != dst[m - 1]) dst[m++] = dst[i];
+    w_at += m;
+    g->ucell_ptr[e + 1] = w_at;
+    if (m < 2) continue;
+    if (star_threshold > 0 && m > star_threshold) {
+      num_star += 1;
+      z += 2 * m;
+    } else {
+      z += m * (m - 1);
+    }
+  }
+  g->num_virtual = num_star;
+  g->num_rows = num_cells + num_star;
+  g->virt_net = (int32_t *)malloc(sizeof(int32_t) * (size_t)(num_star > 0 ? num_star : 1));
+  triple *t = (triple *)malloc(sizeof(triple) * (size_t)(z > 0 ? z : 1));
+  if (!g->virt_net || !t) { free(t); oracle_free(g); return ORACLE_ENOMEM; }
+
+  /* O2: expansion into directed (row, col, net, weight) entries. */
+  int64_t k = 0, v = 0;
+  for (int64_t e = 0; e < num_nets; ++e) {
+    int64_t a = g->ucell_ptr[e], m = g->ucell_ptr[e + 1] - a;
+    const int32_t *c = g->ucell + a;
+    if (m < 2) continue;
+    if (star_threshold > 0 && m > star_threshold) {
+      int32_t vid = (int32_t)(num_cells + v);
+      double gam = star_weight(m, weight_model);
+      g->virt_net[v++] = (int32_t)e;
+      for (int64_t i = 0; i < m; ++i) {
+        t[k].row = c[i]; t[k].col = vid; t[k].net = (int32_t)e; t[k].w = gam; ++k;
+        t[k].row = vid; t[k].col = c[i]; t[k].net = (int32_t)e; t[k].w = gam; ++k;
+      }
+    } else {
+      double wm = clique_weight(m, weight_model);
+      for (int64_t i = 0; i < m; ++i)
+        for (int64_t j = 0; j < m; ++j) {
+          if (i == j) continue;
+          t[k].row = c[i]; t[k].col = c[j]; t[k].net = (int32_t)e; t[k].w = wm; ++k;
+        }
+    }
+  }
+
+  /* O3: sort by (row, col, net); merge equal (row, col) left to right. */
+  qsort(t, (size_t)z, sizeof(triple), cmp_triple);
+  int64_t nnz = 0;
+  for (int64_t i = 0; i < z; ++i)
+    if (i == 0 || t[i].row != t[i - 1].row || t[i].col != t[i - 1].col) ++nnz;
+  g->nnz = nnz;
+  g->row_ptr = (int64_t *)calloc((size_t)(g->num_rows + 1), sizeof(int64_t));
+  g->col = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+  g->w = (double *)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+  g->deg = (double *)calloc((size_t)(g->num_rows > 0 ? g->num_rows : 1), sizeof(double));
+  if (!g->row_ptr || !g->col || !g->w || !g->deg) { free(t); oracle_free(g); return ORACLE_ENOMEM; }
+  int64_t q = -1;
+  for (int64_t i = 0; i < z; ++i) {
+    if (i == 0 || t[i].row != t[i - 1].row || t[i].col != t[i - 1].col) {
+      ++q;
+      g->col[q] = t[i].col;
+      g->w[q] = t[i].w;
+      g->row_ptr[t[i].row + 1] += 1;
+    } else {
+      g->w[q] = g->w[q] + t[i].w;
+    }
+  }
+  free(t);
+  for (int64_t r = 0; r < g->num_rows; ++r) g->row_ptr[r + 1] += g->row_ptr[r];
+
+  /* O4: d_i = sum of row i's weights, ascending column. */
+  for (int64_t r = 0; r < g->num_rows; ++r) {
+    double d = 0.0;
+    for (int64_t p = g->row_ptr[r]; p < g->row_ptr[r + 1]; ++p) d = d + g->w[p];
+    g->deg[r] = d;
+  }
+  *out = g;
+  return ORACLE_OK;
+}
+
+void oracle_sizes(const oracle_graph *g, int64_t *sizes /* [N, V, R, nnz] */) {
+  sizes[0] = g->num_cells;
+  sizes[1] = g->num_virtual;
+  sizes[2] = g->num_rows;
+  sizes[3] = g->nnz;
+}
+
+void oracle_export(const oracle_graph *g, int64_t *row_ptr, int32_t *col, double *w,
+                   double *deg, int32_t *virt_net) {
+  if (row_ptr) memcpy(row_ptr, g->row_ptr, sizeof(int64_t) * (size_t)(g->num_rows + 1));
+  if (col) memcpy(col, g->col, sizeof(int32_t) * (size_t)g->nnz);
+  if (w) memcpy(w, g->w, sizeof(double) * (size_t)g->nnz);
+  if (deg) memcpy(deg, g->deg, sizeof(double) * (size_t)g->num_rows);
+  if (virt_net) memcpy(virt_net, g->virt_net, sizeof(int32_t) * (size_t)g->num_virtual);
+}
+
+/* Step O5: entries of A~_sigma.  a[p] for the off-diagonal entries of A in CSR
+ * order, delta[i] for the diagonal (the self-loop sigma, normalised). */
+int oracle_normalise(const oracle_graph *g, double sigma, double *a, double *delta) {
+  if (!(sigma >= 0.0)) return ORACLE_EINVAL;
+  int64_t rows = g->num_rows;
+  double *s = (double *)malloc(sizeof(double) * (size_t)(rows > 0 ? rows : 1));
+  if (!s) return ORACLE_ENOMEM;
+  for (int64_t i = 0; i < rows; ++i) {
+    double ti = g->deg[i] + sigma;
+    s[i] = (ti == 0.0) ? 0.0 : 1.0 / sqrt(ti);
+  }
+  for (int64_t i = 0; i < rows; ++i) {
+    for (int64_t p = g->row_ptr[i]; p < g->row_ptr[i + 1]; ++p)
+      a[p] = (g->w[p] * s[i]) * s[g->col[p]];
+    delta[i] = (sigma * s[i]) * s[i];
+  }
+  free(s);
+  return ORACLE_OK;
+}
+
+/* One product y = A~_sigma x over R rows, c columns (row-major, ld = c). */
+static void oracle_product(const oracle_graph *g, const double *a, const double *delta,
+                           const double *x, double *y, int64_t c) {
+  for (int64_t i = 0; i < g->num_rows; ++i) {
+    for (int64_t q = 0; q < c; ++q) {
+      double acc = 0.0;
+      for (int64_t p = g->row_ptr[i]; p < g->row_ptr[i + 1]; ++p)
+        acc = acc + a[p] * x[(int64_t)g->col[p] * c + q];
+      y[i * c + q] = acc + delta[i] * x[i * c + q];
+    }
+  }
+}
+
+/* Steps O6-O8.  x_in: N x c (ld = c).  Terms (sigma_t, k_t, alpha_t).
+ * y_out: N x c.  fixed (nullable): rows with fixed[i] != 0 are copied from
+ * x_in after filtering. */
+int oracle_filter(const oracle_graph *g, int64_t num_terms, const double *sigma,
+                  const int32_t *order, const double *alpha, const double *x_in,
+                  int64_t c, const uint8_t *fixed, double *y_out) {
+  if (num_terms < 1 || c < 1) return ORACLE_EINVAL;
+  for (int64_t t = 0; t < num_terms; ++t)
+    if (!(sigma[t] >= 0.0) || order[t] < 1) return ORACLE_EINVAL;
+  int64_t rows = g->num_rows, n = g->num_cells;
+  size_t rc = (size_t)(rows > 0 ? rows : 1) * (size_t)c;
+  double *x0 = (double *)malloc(sizeof(double) * rc);
+  double *xa = (double *)malloc(sizeof(double) * rc);
+  double *xb = (double *)malloc(sizeof(double) * rc);
+  double *saved = (double *)malloc(sizeof(double) * rc * (size_t)num_terms);
+  double *a = (double *)malloc(sizeof(double) * (size_t)(g->nnz > 0 ? g->nnz : 1));
+  double *delta = (double *)malloc(sizeof(double) * (size_t)(rows > 0 ? rows : 1));
+  int *done = (int *)calloc((size_t)num_terms, sizeof(int));
+  int status = ORACLE_OK;
+  if (!x0 || !xa || !xb || !saved || !a || !delta || !done) { status = ORACLE_ENOMEM; goto out; }
+
+  /* O6: real rows from the input, virtual rows at the mean of their cells. */
+  memcpy(x0, x_in, sizeof(double) * (size_t)n * (size_t)c);
+  for (int64_t v = 0; v < g->num_virtual; ++v) {
+    int64_t e = g->virt_net[v];
+    int64_t lo = g->ucell_ptr[e], hi = g->ucell_ptr[e + 1];
+    for (int64_t q = 0; q < c; ++q) {
+      double sum = 0.0;
+      for (int64_t p = lo; p < hi; ++p) sum = sum + x_in[(int64_t)g->ucell[p] * c + q];
+      x0[(n + v) * c + q] = sum / (double)(hi - lo);
+    }
+  }
+
+  /* O7: for every distinct sigma (ascending), repeated products. */
+  for (;;) {
+    double cur = 0.0;
+    int found = 0;
+    for (int64_t t = 0; t < num_terms; ++t)
+      if (!done[t] && (!found || sigma[t] < cur)) { cur = sigma[t]; found = 1; }
+    if (!found) break;
+    int32_t kmax = 0;
+    for (int64_t t = 0; t < num_terms; ++t)
+      if (!done[t] && sigma[t] == cur && order[t] > kmax) kmax = order[t];
+    status = oracle_normalise(g, cur, a, delta);
+    if (status != ORACLE_OK) goto out;
+    memcpy(xa, x0, sizeof(double) * (size_t)rows * (size_t)c);
+    for (int32_t k = 1; k <= kmax; ++k) {
+      oracle_product(g, a, delta, xa, xb, c);
+      double *tmp = xa; xa = xb; xb = tmp;
+      for (int64_t t = 0; t < num_terms; ++t)
+        if (!done[t] && sigma[t] == cur && order[t] == k)
+          memcpy(saved + (size_t)t * rc, xa, sizeof(double) * (size_t)rows * (size_t)c);
+    }
+    for (int64_t t = 0; t < num_terms; ++t)
+      if (sigma[t] == cur) done[t] = 1;
+  }
+
+  /* O8: g' = sum_t alpha_t x^{k_t}_{sigma_t}, in term order; real rows only. */
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t q = 0; q < c; ++q) {
+      double acc = 0.0;
+      for (int64_t t = 0; t < num_terms; ++t)
+        acc = acc + alpha[t] * saved[(size_t)t * rc + (size_t)(i * c + q)];
+      y_out[i * c + q] = (fixed && fixed[i]) ? x_in[i * c + q] : acc;
+    }
+out:
+  free(x0); free(xa); free(xb); free(saved); free(a); free(delta); free(done);
+  return status;
+}

@@ -1,0 +1,146 @@
+"""ctypes wrapper over the C oracle (test infrastructure only).
+
+Only the tests, the package smoke check and the benchmark's CPU-baseline leg
+may use this module.  Every array it returns is float64 / int64 / int32 numpy.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+
+def load(path: Optional[str] = None):
+    """Load the oracle library, compiling it first if nothing is built."""
+    global _lib
+    if path is None and _lib is not None:
+        return _lib
+    p = path or _build.LIB
+    if not os.path.exists(p):
+        _build.build(p)
+    lib = C.CDLL(p)
+    i64, i32 = C.c_int64, C.c_int32
+    vp = C.c_void_p
+    lib.oracle_build.argtypes = [i64, i64, i64, vp, vp, C.c_int, i64, C.POINTER(vp)]
+    lib.oracle_build.restype = C.c_int
+    lib.oracle_free.argtypes = [vp]
+    lib.oracle_free.restype = None
+    lib.oracle_sizes.argtypes = [vp, vp]
+    lib.oracle_sizes.restype = None
+    lib.oracle_export.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.oracle_export.restype = None
+    lib.oracle_normalise.argtypes = [vp, C.c_double, vp, vp]
+    lib.oracle_normalise.restype = C.c_int
+    lib.oracle_filter.argtypes = [vp, i64, vp, vp, vp, vp, i64, vp, vp]
+    lib.oracle_filter.restype = C.c_int
+    if path is None:
+        _lib = lib
+    return lib
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+W_INV_M1 = 0
+W_TWO_OVER_M = 1
+
+
+@dataclasses.dataclass
+class OracleGraph:
+    num_cells: int
+    num_virtual: int
+    row_ptr: np.ndarray  # int64[R+1]
+    col: np.ndarray  # int32[nnz]
+    w: np.ndarray  # float64[nnz]
+    deg: np.ndarray  # float64[R]
+    virt_net: np.ndarray  # int32[V]
+    handle: "C.c_void_p" = None
+    lib: object = None
+
+    @property
+    def num_rows(self) -> int:
+        return self.num_cells + self.num_virtual
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.shape[0])
+
+    def close(self):
+        if self.handle is not None:
+            self.lib.oracle_free(self.handle)
+            self.handle = None
+
+    def __del__(self):  # pragma: no cover - best effort
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def normalise(self, sigma: float):
+        a = np.empty(self.nnz, dtype=np.float64)
+        d = np.empty(self.num_rows, dtype=np.float64)
+        rc = self.lib.oracle_normalise(self.handle, float(sigma), _ptr(a), _ptr(d))
+        if rc:
+            raise OracleError(f"oracle_normalise failed ({rc})")
+        return a, d
+
+    def filter(self, x: np.ndarray, sigma: Sequence[float], order: Sequence[int],
+               alpha: Sequence[float], fixed: Optional[np.ndarray] = None) -> np.ndarray:
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        if x.ndim == 1:
+            x = x[:, None]
+        if x.shape[0] != self.num_cells:
+            raise OracleError("signal rows != cells")
+        c = x.shape[1]
+        s = np.ascontiguousarray(sigma, dtype=np.float64)
+        k = np.ascontiguousarray(order, dtype=np.int32)
+        al = np.ascontiguousarray(alpha, dtype=np.float64)
+        if not (s.shape == k.shape == al.shape):
+            raise OracleError("term arrays differ in length")
+        fx = None if fixed is None else np.ascontiguousarray(fixed, dtype=np.uint8)
+        y = np.empty_like(x)
+        rc = self.lib.oracle_filter(self.handle, s.shape[0], _ptr(s), _ptr(k), _ptr(al),
+                                    _ptr(x), c, _ptr(fx), _ptr(y))
+        if rc:
+            raise OracleError(f"oracle_filter failed ({rc})")
+        return y
+
+
+def build_graph(num_cells: int, net_ptr: np.ndarray, pin_cell: np.ndarray, *,
+                weight_model: int = W_INV_M1, star_threshold: int = 0,
+                lib=None) -> OracleGraph:
+    lib = lib or load()
+    net_ptr = np.ascontiguousarray(net_ptr, dtype=np.int64)
+    pin_cell = np.ascontiguousarray(pin_cell, dtype=np.int32)
+    h = C.c_void_p()
+    rc = lib.oracle_build(int(num_cells), net_ptr.shape[0] - 1, pin_cell.shape[0],
+                          _ptr(net_ptr), _ptr(pin_cell), int(weight_model),
+                          int(star_threshold), C.byref(h))
+    if rc:
+        raise OracleError(f"oracle_build failed ({rc})")
+    sizes = np.zeros(4, dtype=np.int64)
+    lib.oracle_sizes(h, _ptr(sizes))
+    n, v, r, nnz = (int(t) for t in sizes)
+    row_ptr = np.empty(r + 1, dtype=np.int64)
+    col = np.empty(nnz, dtype=np.int32)
+    w = np.empty(nnz, dtype=np.float64)
+    deg = np.empty(r, dtype=np.float64)
+    vn = np.empty(v, dtype=np.int32)
+    lib.oracle_export(h, _ptr(row_ptr), _ptr(col), _ptr(w), _ptr(deg), _ptr(vn))
+    return OracleGraph(n, v, row_ptr, col, w, deg, vn, h, lib)
+
+
+def build_netlist(netlist, **kw) -> OracleGraph:
+    return build_graph(netlist.num_cells, netlist.net_ptr, netlist.pin_cell, **kw)

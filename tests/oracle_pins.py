@@ -1,0 +1,291 @@
+"""Pins that tie the CPU oracle to the paper and to mathematics.
+
+Each ``pin_*`` function takes an oracle library handle and raises
+``AssertionError`` when the oracle disagrees with what the paper or the
+mathematics fixes.  ``test_oracle_pins.py`` runs them on the real oracle and
+``test_oracle_mutants.py`` runs them on deliberately broken copies of the
+oracle source, each of which must fail at least one pin.
+"""
+from __future__ import annotations
+
+import os
+from fractions import Fraction
+
+import numpy as np
+import scipy.sparse as sp
+
+from oracle import dense as D
+from oracle import oracle as O
+from paper_2502_17632_amd import workload as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _read_golden(name):
+    out = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            k, v = (t.strip() for t in line.split("=", 1))
+            out[k] = [Fraction(t) for t in v.split()]
+    return out
+
+
+def _random_netlist(rng, n_cells, n_nets, max_pins, dup_prob=0.2):
+    """Tiny netlists with the awkward cases: repeated pins on one net, 0- and
+    1-pin nets, parallel nets and isolated cells."""
+    sizes = rng.integers(0, max_pins + 1, size=n_nets)
+    pins = []
+    for m in sizes:
+        cells = list(rng.integers(0, n_cells, size=m))
+        if m >= 2 and rng.random() < dup_prob:
+            cells.append(cells[0])  # a repeated pin
+        pins.append(cells)
+    if n_nets >= 2 and len(pins[0]) >= 2:
+        pins[1] = list(pins[0][:2])  # a parallel net on one pair
+    net_ptr = np.zeros(n_nets + 1, dtype=np.int64)
+    net_ptr[1:] = np.cumsum([len(p) for p in pins])
+    pin_cell = np.array([c for p in pins for c in p], dtype=np.int32)
+    return net_ptr, pin_cell
+
+
+def _dense_from(g: O.OracleGraph) -> np.ndarray:
+    r = g.num_rows
+    a = np.zeros((r, r))
+    for i in range(r):
+        for p in range(g.row_ptr[i], g.row_ptr[i + 1]):
+            a[i, g.col[p]] = g.w[p]
+    return a
+
+
+def _csr(g: O.OracleGraph, vals):
+    return sp.csr_matrix((vals, g.col, g.row_ptr), shape=(g.num_rows, g.num_rows))
+
+
+# -------------------------------------------------------------------------
+
+
+def pin_golden_two_cell(lib):
+    """The hand-derived two-cell example of the paper's filter."""
+    gd = _read_golden("two_cell_paper_filter.txt")
+    g = O.build_graph(int(gd["num_cells"][0]), np.array(gd["net_ptr"], dtype=np.int64),
+                      np.array(gd["pin_cell"], dtype=np.int32), lib=lib)
+    x = np.array([float(v) for v in gd["x"]])[:, None]
+    y = g.filter(x, [float(v) for v in gd["sigma"]], [int(v) for v in gd["order"]],
+                 [float(v) for v in gd["alpha"]])
+    exp = np.array([float(v) for v in gd["expected"]])
+    assert np.allclose(y[:, 0], exp, rtol=0, atol=1e-15), (y[:, 0], exp)
+    for s, k, key in ((2.0, 2, "offdiag_A2_pow2"), (4.0, 2, "offdiag_A4_pow2"),
+                      (4.0, 4, "offdiag_A4_pow4")):
+        yk = g.filter(x, [s], [k], [1.0])
+        assert abs(yk[0, 0] - float(gd[key][0])) <= 1e-15, (s, k, yk[0, 0])
+    g.close()
+
+
+def pin_clique_closed_form(lib):
+    """One net of M cells: every cell has degree (M-1) w, and
+    A~^k x = mean(x) 1 + mu^k (x - mean(x) 1), mu = (sigma - w)/(d + sigma)."""
+    rng = np.random.default_rng(1)
+    for model in (O.W_INV_M1, O.W_TWO_OVER_M):
+        for m in (2, 3, 5, 9):
+            w = 2.0 / m if model == O.W_TWO_OVER_M else 1.0 / (m - 1)
+            d = (m - 1) * w
+            perm = rng.permutation(m).astype(np.int32)
+            g = O.build_graph(m, np.array([0, m], dtype=np.int64), perm,
+                              weight_model=model, lib=lib)
+            assert g.nnz == m * (m - 1)
+            x = rng.normal(size=(m, 2)) * 10 + 3
+            for s in (0.5, 2.0, 4.0):
+                mu = (s - w) / (d + s)
+                for k in (1, 2, 3, 7):
+                    y = g.filter(x, [s], [k], [1.0])
+                    xb = x.mean(axis=0, keepdims=True)
+                    exp = xb + mu ** k * (x - xb)
+                    assert np.allclose(y, exp, rtol=1e-13, atol=1e-13), (model, m, s, k)
+            g.close()
+
+
+def pin_hand_built(lib):
+    """Hand-built weights and degrees (clique model, w = 1/(M-1))."""
+    g = O.build_graph(4, np.array([0, 4]), np.array([3, 1, 0, 2]), lib=lib)
+    assert g.nnz == 12 and np.all(g.w == 1.0 / 3.0) and np.all(g.deg == 1.0)
+    g = O.build_graph(2, np.array([0, 2, 4]), np.array([0, 1, 1, 0]), lib=lib)
+    assert list(g.col) == [1, 0] and list(g.w) == [2.0, 2.0]
+    g = O.build_graph(3, np.array([0, 3, 5]), np.array([0, 1, 2, 1, 0]), lib=lib)
+    a = _dense_from(g)
+    assert a[0, 1] == 1.5 and a[1, 0] == 1.5 and a[0, 2] == 0.5 and a[1, 2] == 0.5
+    assert list(g.deg) == [2.0, 2.0, 1.0]
+    # repeated pins and a single-cell net add nothing
+    g = O.build_graph(3, np.array([0, 3, 5]), np.array([0, 0, 1, 2, 2]), lib=lib)
+    assert g.nnz == 2 and list(g.w) == [1.0, 1.0] and g.deg[2] == 0.0
+
+
+def pin_brute_force_structure(lib):
+    """CSR, weights and degrees equal (bitwise) a dense matrix accumulated
+    straight from the net model, for both weight models, with and without
+    star expansion."""
+    rng = np.random.default_rng(2)
+    for trial in range(40):
+        n = int(rng.integers(1, 25))
+        e = int(rng.integers(0, 30))
+        net_ptr, pin_cell = _random_netlist(rng, n, e, 9)
+        for model in (O.W_INV_M1, O.W_TWO_OVER_M):
+            for thr in (0, 3, 5):
+                g = O.build_graph(n, net_ptr, pin_cell, weight_model=model,
+                                  star_threshold=thr, lib=lib)
+                a, star = D.dense_adjacency(n, net_ptr, pin_cell, weight_model=model,
+                                            star_threshold=thr)
+                assert g.num_rows == a.shape[0], (trial, model, thr)
+                assert list(g.virt_net) == star
+                rows, cols = np.nonzero(a)
+                ptr = np.zeros(a.shape[0] + 1, dtype=np.int64)
+                np.add.at(ptr, rows + 1, 1)
+                ptr = np.cumsum(ptr)
+                assert np.array_equal(g.row_ptr, ptr)
+                assert np.array_equal(g.col, cols.astype(np.int32))
+                assert np.array_equal(g.w.view(np.uint64), a[rows, cols].view(np.uint64))
+                dd = D.dense_degree(a)
+                assert np.array_equal(g.deg.view(np.uint64), dd.view(np.uint64))
+                g.close()
+
+
+def pin_spectral(lib):
+    """The filter equals U h(Lambda) U^T x from a dense eigendecomposition of
+    the augmented normalised Laplacian, h(l) = sum alpha (1 - l)^k."""
+    rng = np.random.default_rng(3)
+    cases = [([4.0] * 4, [1, 2, 4, 8], [0.25] * 4),
+             ([2.0, 4.0, 4.0], [2, 2, 4], [0.1, 0.7, 0.2]),
+             ([0.0, 1.0, 3.5], [3, 1, 5], [0.5, -0.25, 0.75])]
+    for trial in range(24):
+        n = int(rng.integers(2, 30))
+        e = int(rng.integers(1, 40))
+        net_ptr, pin_cell = _random_netlist(rng, n, e, 8)
+        thr = int(rng.choice([0, 3, 4]))
+        model = int(rng.integers(0, 2))
+        g = O.build_graph(n, net_ptr, pin_cell, weight_model=model, star_threshold=thr,
+                          lib=lib)
+        a, star = D.dense_adjacency(n, net_ptr, pin_cell, weight_model=model,
+                                    star_threshold=thr)
+        x = rng.normal(size=(n, 2)) * 30 + 500
+        xe = D.extend_signal(x, net_ptr, pin_cell, star)
+        for sig, k, al in cases:
+            y = g.filter(x, sig, k, al)
+            ref = D.spectral_filter(a, xe, sig, k, al)[:n]
+            err = np.abs(y - ref).max() / max(np.abs(ref).max(), 1e-300)
+            assert err <= 1e-12, (trial, sig, k, err)
+        g.close()
+
+
+def pin_theorem1_fixed_point(lib):
+    """Theorem 1 with self-loops: sqrt(d + sigma) is an eigenvector of A~_sigma
+    with eigenvalue 1; so with one sigma and weights summing to one it is a
+    fixed point of the whole filter."""
+    nl = W.make_netlist(600, 20, 700, dist="zipf", param=2.2, cap=40, seed=5)
+    g = O.build_netlist(nl, lib=lib)
+    for s in (0.5, 2.0, 4.0):
+        a, dl = g.normalise(s)
+        m = _csr(g, a) + sp.diags(dl)
+        v = np.sqrt(g.deg + s)
+        assert np.allclose(m @ v, v, rtol=1e-13, atol=0)
+        y = g.filter(np.stack([v, 2 * v], axis=1), [s] * 3, [1, 3, 6], [0.2, 0.5, 0.3])
+        assert np.allclose(y, np.stack([v, 2 * v], axis=1), rtol=1e-12, atol=0)
+    g.close()
+
+
+def pin_spectrum(lib):
+    """Eigenvalues of A~_sigma lie in [1 - 2 max d/(d + sigma), 1] (since the
+    Laplacian is at most 2D) and a larger self-loop lowers the largest
+    eigenvalue of the normalised Laplacian (Section 3.2.1, Fig. 2a)."""
+    rng = np.random.default_rng(6)
+    net_ptr, pin_cell = _random_netlist(rng, 40, 60, 6, dup_prob=0.0)
+    g = O.build_graph(40, net_ptr, pin_cell, lib=lib)
+    tops = []
+    for s in (0.0, 1.0, 2.0, 3.0):
+        a, dl = g.normalise(s)
+        m = (_csr(g, a) + sp.diags(dl)).toarray()
+        assert np.allclose(m, m.T, rtol=4e-16, atol=0)
+        lam = np.linalg.eigvalsh(m)
+        conn = g.deg > 0
+        lo = 1.0 - 2.0 * np.max(g.deg[conn] / (g.deg[conn] + s))
+        assert lam.max() <= 1.0 + 1e-12 and lam.min() >= lo - 1e-12, (s, lam.min(), lo)
+        assert abs(lam.max() - 1.0) < 1e-12
+        tops.append(1.0 - lam.min())
+    assert all(tops[i + 1] < tops[i] for i in range(len(tops) - 1)), tops
+    g.close()
+
+
+def pin_isolated_and_fixed(lib):
+    """An isolated cell keeps (sum alpha) x with a self-loop and vanishes
+    without one; fixed rows are restored from the input on request."""
+    g = O.build_graph(4, np.array([0, 2, 4]), np.array([0, 1, 1, 2]), lib=lib)
+    x = np.array([[1.0, 2.0], [3.0, 4.0], [5.0, 6.0], [7.0, 8.0]])
+    y = g.filter(x, [2.0, 4.0], [3, 1], [0.3, 0.5])
+    assert np.allclose(y[3], 0.8 * x[3], rtol=1e-15)
+    y0 = g.filter(x, [0.0], [2], [1.0])
+    assert np.all(y0[3] == 0.0)
+    fixed = np.array([0, 1, 0, 1], dtype=np.uint8)
+    yf = g.filter(x, [2.0], [2], [1.0], fixed=fixed)
+    yn = g.filter(x, [2.0], [2], [1.0])
+    assert np.array_equal(yf[[1, 3]], x[[1, 3]]) and np.array_equal(yf[[0, 2]], yn[[0, 2]])
+    g.close()
+
+
+def pin_star_schur(lib):
+    """A star of weight M w(M) around a virtual node is the clique exactly:
+    eliminating the virtual nodes from the star graph's Laplacian (Schur
+    complement) gives the clique graph's Laplacian."""
+    rng = np.random.default_rng(7)
+    for model in (O.W_INV_M1, O.W_TWO_OVER_M):
+        net_ptr, pin_cell = _random_netlist(rng, 30, 25, 9)
+        gc = O.build_graph(30, net_ptr, pin_cell, weight_model=model, lib=lib)
+        gs = O.build_graph(30, net_ptr, pin_cell, weight_model=model, star_threshold=3,
+                           lib=lib)
+        assert gs.num_virtual > 0
+        lc = np.diag(gc.deg) - _dense_from(gc)
+        ls = np.diag(gs.deg) - _dense_from(gs)
+        n = 30
+        schur = ls[:n, :n] - ls[:n, n:] @ np.linalg.solve(ls[n:, n:], ls[n:, :n])
+        assert np.allclose(schur, lc, rtol=0, atol=1e-12)
+        gc.close(); gs.close()
+
+
+def pin_generated_invariants(lib):
+    """On a generated clique-model netlist: weights are symmetric bit for bit,
+    with w = 1/(M-1) every cell's degree is the number of nets it is on, and
+    the degrees sum to the total pin count of the kept nets."""
+    nl = W.tiny(seed=3)
+    g = O.build_netlist(nl, lib=lib)
+    a = _csr(g, g.w)
+    assert (a != a.T).nnz == 0
+    at = a.T.tocsr()
+    at.sort_indices()
+    assert np.array_equal(at.data.view(np.uint64), g.w.view(np.uint64))
+    m = np.diff(nl.net_ptr)
+    owner = np.repeat(np.arange(nl.num_nets), m)
+    kept = m >= 2
+    inc = np.bincount(nl.pin_cell[kept[owner]], minlength=nl.num_cells)
+    assert np.allclose(g.deg, inc, rtol=4e-16 * 8, atol=0)
+    assert abs(g.deg.sum() - m[kept].sum()) <= 1e-9 * m.sum()
+    g.close()
+
+
+def pin_invalid_input(lib):
+    """Malformed netlists are refused."""
+    import pytest
+    with pytest.raises(O.OracleError):
+        O.build_graph(2, np.array([0, 2]), np.array([0, 2]), lib=lib)
+    with pytest.raises(O.OracleError):
+        O.build_graph(2, np.array([0, 2, 1]), np.array([0, 1]), lib=lib)
+    g = O.build_graph(2, np.array([0, 2]), np.array([0, 1]), lib=lib)
+    with pytest.raises(O.OracleError):
+        g.filter(np.zeros((2, 1)), [-1.0], [1], [1.0])
+    with pytest.raises(O.OracleError):
+        g.filter(np.zeros((2, 1)), [1.0], [0], [1.0])
+
+
+ALL_PINS = [pin_golden_two_cell, pin_clique_closed_form, pin_hand_built,
+            pin_brute_force_structure, pin_spectral, pin_theorem1_fixed_point,
+            pin_spectrum, pin_isolated_and_fixed, pin_star_schur,
+            pin_generated_invariants, pin_invalid_input]

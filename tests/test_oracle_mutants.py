@@ -1,0 +1,49 @@
+"""Each plausible mistake planted in a copy of the oracle's C source must be
+caught by at least one pin (no GPU).  The real oracle is never modified."""
+import os
+import tempfile
+
+import pytest
+
+from oracle import build as B
+from oracle import oracle as O
+
+from oracle_pins import ALL_PINS
+
+MUTANTS = {
+    "drop_self_loop_term": ("y[i * c + q] = acc + delta[i] * x[i * c + q];",
+                            "y[i * c + q] = acc;"),
+    "row_scale_twice": ("a[p] = (g->w[p] * s[i]) * s[g->col[p]];",
+                        "a[p] = (g->w[p] * s[i]) * s[i];"),
+    "weight_one_over_m": ("return 1.0 / (double)(m - 1);", "return 1.0 / (double)m;"),
+    "degree_without_sigma": ("double ti = g->deg[i] + sigma;", "double ti = g->deg[i];"),
+    "no_sqrt": ("1.0 / sqrt(ti)", "1.0 / ti"),
+    "combine_ignores_alpha": ("acc = acc + alpha[t] * saved", "acc = acc + saved"),
+    "no_dedupe": ("if (m == 0 || dst[i] != dst[m - 1]) dst[m++] = dst[i];",
+                  "dst[m++] = dst[i];"),
+    "merge_keeps_last": ("g->w[q] = g->w[q] + t[i].w;", "g->w[q] = t[i].w;"),
+    "star_weight_as_clique": ("return (double)m / (double)(m - 1);",
+                              "return 1.0 / (double)(m - 1);"),
+    "virtual_mean_off_by_one": ("sum / (double)(hi - lo)", "sum / (double)(hi - lo + 1)"),
+    "self_loop_unscaled": ("delta[i] = (sigma * s[i]) * s[i];", "delta[i] = sigma * s[i];"),
+    "fixed_rows_not_restored": ("(fixed && fixed[i]) ? x_in[i * c + q] : acc", "acc"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name):
+    old, new = MUTANTS[name]
+    src = open(B.SRC).read()
+    assert src.count(old) == 1, f"mutation site for {name} not found exactly once"
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "mutant.c")
+        with open(path, "w") as f:
+            f.write(src.replace(old, new))
+        lib = O.load(B.build(os.path.join(d, "libmutant.so"), path))
+        caught = []
+        for pin in ALL_PINS:
+            try:
+                pin(lib)
+            except Exception as exc:  # any failed pin counts
+                caught.append((pin.__name__, type(exc).__name__))
+        assert caught, f"no pin catches mutant {name}"
