@@ -1,0 +1,217 @@
+#!/usr/bin/env python3
+"""Benchmark of the GiFt hot path on one MI355X.
+
+One step = the whole hot path on the large synthetic workload (2,000,000
+movable + 20,000 fixed cells, 2,100,000 nets, pins 2 + Zipf(2.2) capped at
+1000, 90% index-local; nets above 16 cells star-expanded): netlist -> graph
+build (dedupe, expansion, CSR sort/merge, degrees, normalisation) and the
+multi-order filter (sigma 4, orders 1, 2, 4, 8, 16, equal weights, 2 signal
+columns, float32 storage).  The netlist and the signal are resident in HBM
+before the timed region starts.
+
+Prints one JSON line.  ``value`` is filter work per second of whole step:
+sum over the 16 SpMM passes of (stored entries + diagonal) x columns,
+divided by the step time.  The roofline object describes the dominant
+kernel, the non-final SpMM pass, timed per launch with HIP events on its own
+stream by the library's profiler during the timed steps.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "filter nnz·cols/s + achieved HBM GB/s vs peak; p50/p99 request latency"
+COUNTERS = os.path.join(ROOT, "profiles", "spmm_large_f32_counters.txt")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def host_cpu():
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def counter_traffic():
+    """HBM bytes per SpMM launch measured with rocprofv3 counters, if they were
+    taken on the current kernel source."""
+    src = os.path.join(ROOT, "paper_2502_17632_amd", "csrc", "filter.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    try:
+        kv = {}
+        for line in open(COUNTERS):
+            if "=" in line and not line.startswith("#"):
+                k, v = line.strip().split("=", 1)
+                kv[k.strip()] = v.strip()
+        if kv.get("filter_hip_sha256") == sha:
+            return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        pass
+    return None
+
+
+def filter_work(info, passes, cols):
+    """(nnz + R) * cols for every pass but the last, (nnz_cells + N) * cols for
+    the last one (which computes the cell rows only)."""
+    full = (info["nnz"] + info["num_rows"]) * cols
+    return full * (passes - 1) + (info["nnz_cells"] + info["num_cells"]) * cols
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "f16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the extra measurements")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path "
+              f"(--gpus {args.gpus} requested)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2502_17632_amd as gift
+    from paper_2502_17632_amd import workload as W
+
+    torch.cuda.set_device(0)
+    orders = [1, 2, 4, 8, 16]
+    terms = ([4.0] * len(orders), orders, [1.0 / len(orders)] * len(orders))
+    thr = 16
+    log("[bench] generating the large workload")
+    nl = W.large()
+    x_host = W.make_signal(nl)
+    net_ptr = torch.tensor(nl.net_ptr, device="cuda")
+    pin_cell = torch.tensor(nl.pin_cell, device="cuda")
+    x = torch.tensor(x_host, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+
+    def step():
+        g = gift.build_graph(nl.num_cells, net_ptr, pin_cell, star_threshold=thr,
+                             storage=args.storage, sigmas=[4.0])
+        gift.filter_placement(g, *terms, x, out=y)
+        info = g.info()
+        g.close()
+        return info
+
+    log("[bench] warmup")
+    info = None
+    for _ in range(args.warmup):
+        info = step()
+    torch.cuda.synchronize()
+    if info is None:
+        info = step()
+        torch.cuda.synchronize()
+    info["nnz_cells"] = None
+    # nnz of the cell rows: from the exported row pointer of one graph
+    g = gift.build_graph(nl.num_cells, net_ptr, pin_cell, star_threshold=thr,
+                         storage=args.storage, sigmas=[4.0])
+    row_ptr, _, _, _ = g.export()
+    info["nnz_cells"] = int(row_ptr[nl.num_cells])
+
+    log(f"[bench] timing {args.steps} steps")
+    gift.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    spmm = gift.profile_collect("spmm")
+    fin = gift.profile_collect("spmm_final")
+    bld = gift.profile_collect("build")
+    gift.profile_enable(False)
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    work = filter_work(info, max(orders), 2)
+    value = work / (ms_step * 1e-3)
+    avg_ms = spmm["total_ms"] / max(spmm["launches"], 1)
+    bytes_launch = spmm["bytes"] / max(spmm["launches"], 1)
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    traffic = counter_traffic()
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "kernel": "k_spmm (non-final pass)",
+                "bytes_per_launch": bytes_launch, "avg_launch_us": round(avg_ms * 1e3, 2),
+                "launches": spmm["launches"]}
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "nnz·cols/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.storage, "data": "synthetic",
+        "config": {"workload": "large: 2M+20k cells, 2.1M nets, Zipf(2.2) pins <= 1000, "
+                               "90% local; star above 16 cells; sigma 4, orders 1,2,4,8,16, "
+                               "equal weights; 2 columns",
+                   "cells": nl.num_cells, "nets": nl.num_nets, "rows": info["num_rows"],
+                   "nnz": info["nnz"], "cols": 2, "storage": args.storage,
+                   "passes": max(orders)},
+        "roofline": roofline,
+        "breakdown": {
+            "build_ms": round(bld["total_ms"] / max(bld["launches"], 1), 4),
+            "filter_final_pass_us": round(fin["total_ms"] / max(fin["launches"], 1) * 1e3, 2),
+            "spmm_pass_us": round(avg_ms * 1e3, 2),
+        },
+    }
+
+    if not args.no_extra:
+        # the filter alone on a resident graph
+        for _ in range(3):
+            gift.filter_placement(g, *terms, x, out=y)
+        torch.cuda.synchronize()
+        reps = 20
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(reps):
+            gift.filter_placement(g, *terms, x, out=y)
+        ev1.record()
+        torch.cuda.synchronize()
+        f_ms = ev0.elapsed_time(ev1) / reps
+        out["filter_only"] = {"ms": round(f_ms, 4), "nnz_cols_per_s": work / (f_ms * 1e-3)}
+    g.close()
+
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        log("[bench] timing the CPU oracle (one full step, single thread)")
+        model, ncpu = host_cpu()
+        xo = x_host.astype(np.float32).astype(np.float64)
+        t0 = time.perf_counter()
+        og = O.build_netlist(nl, star_threshold=thr)
+        t1 = time.perf_counter()
+        og.filter(xo, *terms)
+        t2 = time.perf_counter()
+        og_work = filter_work({"nnz": og.nnz, "num_rows": og.num_rows, "num_cells": og.num_cells,
+                               "nnz_cells": int(og.row_ptr[og.num_cells])}, max(orders), 2)
+        out["cpu_baseline"] = {
+            "value": og_work / (t2 - t0), "unit": "nnz·cols/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "one whole step of the same large workload (oracle build + 16-pass "
+                      "filter, float64), single-threaded C",
+            "build_s": round(t1 - t0, 3), "filter_s": round(t2 - t1, 3),
+            "host_cpu": model, "host_threads": ncpu}
+        og.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,263 @@
+/*
+ * gift.h -- C ABI of the GiFt graph-filter placement library (AMD MI355X,
+ * gfx950).
+ *
+ * GiFt ("The Power of Graph Signal Processing for Chip Placement
+ * Acceleration", ICCAD'24) computes an initial cell placement by low-pass
+ * filtering the cells' location signal on the circuit graph:
+ *
+ *     g' = sum_t alpha_t  A~_{sigma_t}^{k_t}  g                (eq. proposed_filter)
+ *     A~_sigma = (D + sigma I)^-1/2 (A + sigma I) (D + sigma I)^-1/2
+ *                                                             (eq. A_formulation)
+ *
+ * where A is the weighted adjacency of the netlist under the clique net model
+ * (Section 3.2, the paragraph after Algorithm 1) and D its degree matrix
+ * (Section 2.1).  The library has two steps:
+ *
+ *   gift_build_graph       netlist -> resident normalised graph
+ *   gift_filter_placement  graph + signal -> filtered signal
+ *
+ * plus batched filtering of many graphs in one launch sequence and a
+ * request-serving engine.
+ *
+ * Conventions for every entry point:
+ *   - Every function returns a gift_status and never aborts or throws.  On an
+ *     error gift_last_error() (per host thread) describes it.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Device work is ordered on it.  Functions that must read sizes back
+ *     (gift_build_graph) synchronise that stream before returning; the others
+ *     only enqueue work.
+ *   - Caller-owned buffers stay caller-owned.  Device pointers must point to
+ *     memory of the current HIP device.  Matrices are row-major with a
+ *     leading dimension given in elements.
+ *   - Objects created by the library (graphs, batches, servers) are owned by
+ *     the caller's handle and released only by the matching destroy call.
+ *   - Sizes are limited to fewer than 2^31 rows and 2^31 stored entries per
+ *     graph; larger inputs return GIFT_EUNSUPPORTED.
+ */
+#ifndef GIFT_H
+#define GIFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GIFT_ABI_VERSION 1
+
+typedef enum {
+  GIFT_OK = 0,
+  GIFT_EINVAL = 1,       /* bad argument, malformed netlist, unknown sigma   */
+  GIFT_ENOMEM = 2,       /* a device or host allocation failed               */
+  GIFT_EDEVICE = 3,      /* a HIP runtime call failed (message kept)         */
+  GIFT_EUNSUPPORTED = 4, /* valid but unsupported combination or size       */
+  GIFT_EBUSY = 5         /* object in use (e.g. server still has work)       */
+} gift_status;
+
+/* Element types of stored values and of signals. */
+typedef enum {
+  GIFT_F32 = 0,
+  GIFT_F64 = 1,
+  GIFT_BF16 = 2, /* bfloat16, round-to-nearest-even when stored            */
+  GIFT_F16 = 3   /* IEEE half, round-to-nearest-even when stored           */
+} gift_dtype;
+
+/* Weight a net of M distinct cells adds to each pair of its cells. */
+typedef enum {
+  GIFT_W_INV_M1 = 0,    /* 1/(M-1): every cell of a clique gets degree 1     */
+  GIFT_W_TWO_OVER_M = 1 /* 2/M: the net weight of Section 2.2 (eq. wire_eq)  */
+} gift_weight_model;
+
+typedef enum { GIFT_MEM_HOST = 0, GIFT_MEM_DEVICE = 1 } gift_mem_space;
+
+typedef struct gift_graph gift_graph;
+
+/*
+ * Netlist and graph options for gift_build_graph.
+ *
+ *   num_cells       N >= 0 cells (movable and fixed), rows 0..N-1 of every
+ *                   signal.
+ *   num_nets        E >= 0 nets.
+ *   net_ptr         int64[E+1], net_ptr[0] = 0, non-decreasing: the pins of
+ *                   net e are pin_cell[net_ptr[e] .. net_ptr[e+1]).
+ *   pin_cell        int32[net_ptr[E]], each in [0, N).
+ *   mem_space       where net_ptr and pin_cell live (GIFT_MEM_HOST or
+ *                   GIFT_MEM_DEVICE).  They are read during the call only.
+ *   weight_model    gift_weight_model.
+ *   star_threshold  T >= 0.  A net with more than T distinct cells (T > 0) is
+ *                   expanded as a star: one virtual node joined to each of its
+ *                   cells with weight M*w(M) (the Laplacian of the star with
+ *                   the virtual node eliminated is exactly the clique's).
+ *                   T = 0 expands every net as a clique.  Virtual nodes are
+ *                   rows N..N+V-1 in ascending net order; they are internal
+ *                   and never appear in a signal handed to or returned by the
+ *                   library.
+ *   storage         gift_dtype of the normalised off-diagonal values and of
+ *                   the filter's internal signal iterates.  F32, BF16 and F16
+ *                   accumulate in float32; F64 accumulates in float64.
+ *   num_sigmas      number of self-loop weights to prepare (>= 1).
+ *   sigmas          host double[num_sigmas], each >= 0: the sigma values the
+ *                   filter may use.  More can be added with
+ *                   gift_graph_add_sigma.
+ *
+ * Netlist semantics: repeated pins of one net count once; a net with fewer
+ * than two distinct cells adds nothing; weights of different nets on the same
+ * pair add up.  The degree d_i = sum_j w_ij excludes the self-loop.
+ */
+typedef struct {
+  int64_t num_cells;
+  int64_t num_nets;
+  const int64_t *net_ptr;
+  const int32_t *pin_cell;
+  int32_t mem_space;
+  int32_t weight_model;
+  int64_t star_threshold;
+  int32_t storage;
+  int32_t num_sigmas;
+  const double *sigmas;
+} gift_graph_desc;
+
+/* One filter term alpha * A~_sigma^order (Section 3.2.1, eq. proposed_filter).
+ * order >= 1, sigma >= 0 and prepared in the graph. */
+typedef struct {
+  double sigma;
+  int32_t order;
+  int32_t reserved; /* must be 0 */
+  double alpha;
+} gift_term;
+
+typedef struct {
+  int64_t num_cells;      /* N */
+  int64_t num_virtual;    /* V: star nodes */
+  int64_t num_rows;       /* R = N + V */
+  int64_t nnz;            /* stored off-diagonal entries of A */
+  int64_t bytes_resident; /* device bytes held by the graph */
+  int32_t storage;        /* gift_dtype */
+  int32_t num_sigmas;     /* prepared self-loop weights */
+} gift_graph_info;
+
+/*
+ * gift_build_graph -- netlist -> resident graph (clique net model, Section
+ * 3.2; degrees and Laplacian, Section 2.1; normalisation, eq. A_formulation).
+ *
+ * Builds the canonical CSR of A (rows ascending, columns ascending within a
+ * row, parallel edges summed in ascending net id in float64, no diagonal),
+ * the float64 degrees (summed in ascending column), and for every sigma the
+ * normalised values a_ij = (w_ij s_i) s_j and diagonal (sigma s_i) s_i with
+ * s_i = 1/sqrt(d_i + sigma) (s_i = 0 when d_i + sigma = 0), rounded once to
+ * the storage type.  The structure, weights and degrees are deterministic.
+ * The call synchronises `stream` (it reads sizes back) and returns after the
+ * graph is complete.  Errors: GIFT_EINVAL for a malformed netlist (pin out of
+ * range, net_ptr not starting at 0 or decreasing), negative sizes, sigma < 0,
+ * num_sigmas < 1 or bad enums; GIFT_ENOMEM; GIFT_EDEVICE.  On error *out is
+ * NULL and nothing is leaked.
+ */
+gift_status gift_build_graph(const gift_graph_desc *desc, void *stream, gift_graph **out);
+
+/*
+ * gift_filter_placement -- g' = sum_t alpha_t A~_{sigma_t}^{k_t} g
+ * (eq. proposed_filter; Section 3.2.2 for the role of the result).
+ *
+ *   terms, num_terms  host array of filter terms, num_terms in [1, 64].
+ *   x_in              device, N x num_cols, leading dimension ld_in >=
+ *                     num_cols, element type in_dtype (F32 or F64).
+ *   y_out             device, N x num_cols, ld_out >= num_cols, out_dtype
+ *                     (F32 or F64).  Must not overlap x_in.
+ *   fixed_mask        device uint8[N] or NULL.  Rows with a non-zero mask are
+ *                     copied from x_in to y_out (fixed cells keep their
+ *                     position, Section 4.1); NULL returns the raw filter for
+ *                     every row.
+ *
+ * Powers are formed by repeated sparse products per distinct sigma; virtual
+ * rows start at the mean of their net's cells.  The terms are combined in
+ * float64 in the given order and rounded once to out_dtype.  Asynchronous on
+ * `stream`; device scratch is taken from and returned to the stream-ordered
+ * allocator.  Errors: GIFT_EINVAL (NULL pointers, sizes, order < 1, a sigma
+ * not prepared), GIFT_EUNSUPPORTED (dtype), GIFT_ENOMEM, GIFT_EDEVICE.
+ */
+gift_status gift_filter_placement(const gift_graph *graph, const gift_term *terms,
+                                  int32_t num_terms, const void *x_in, int32_t num_cols,
+                                  int64_t ld_in, int32_t in_dtype, void *y_out,
+                                  int64_t ld_out, int32_t out_dtype,
+                                  const uint8_t *fixed_mask, void *stream);
+
+/* Prepare one more self-loop weight (sigma >= 0).  No-op if already there. */
+gift_status gift_graph_add_sigma(gift_graph *graph, double sigma, void *stream);
+
+gift_status gift_graph_get_info(const gift_graph *graph, gift_graph_info *info);
+
+/*
+ * Copy the graph to host memory (for inspection and tests).  Any pointer may
+ * be NULL.  row_ptr: int64[R+1]; col: int32[nnz]; w: double[nnz] (A's
+ * weights); deg: double[R].  Synchronises `stream`.
+ */
+gift_status gift_graph_export(const gift_graph *graph, int64_t *row_ptr, int32_t *col,
+                              double *w, double *deg, void *stream);
+
+/*
+ * Copy the normalised values for one prepared sigma to host memory, widened
+ * to double: val[nnz] in CSR order and diag[R].  Synchronises `stream`.
+ */
+gift_status gift_graph_export_normalised(const gift_graph *graph, double sigma, double *val,
+                                         double *diag, void *stream);
+
+/*
+ * Release the graph.  Its device memory is returned in stream order on
+ * `stream`: every use of the graph must be ordered before this point on
+ * `stream` (same stream, or an event the stream waits on).
+ */
+gift_status gift_destroy_graph(gift_graph *graph, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Kernel timing (for benchmarks).
+ * ----------------------------------------------------------------------*/
+
+/* Kernel classes timed by the library's event profiler. */
+typedef enum {
+  GIFT_PROF_SPMM = 0,       /* an SpMM pass that stores its iterate          */
+  GIFT_PROF_SPMM_FINAL = 1, /* the last SpMM pass with the fused combine     */
+  GIFT_PROF_BUILD = 2,      /* one whole gift_build_graph call (all kernels) */
+  GIFT_PROF_NUM_CLASSES = 3
+} gift_prof_class;
+
+/*
+ * Enable (on != 0) or disable the event profiler for the calling process.
+ * While enabled, the library records a pair of HIP events on the launch
+ * stream around every launch of the timed classes, at the cost of two event
+ * records per launch.  Enabling clears earlier records.
+ */
+gift_status gift_profile_enable(int32_t on);
+
+/*
+ * Totals since the last enable/collect for one class: number of launches,
+ * summed and per-launch maximum device duration (milliseconds, from the
+ * event pairs) and the summed algorithmic bytes of the launches.  An SpMM
+ * pass counts row_ptr, col and values of the rows it covers, their diagonal,
+ * every signal row read once and the rows it writes (the final pass: the saved
+ * iterates it reads and the output); the build class reports 0 bytes.  Waits
+ * for the recorded events; clears that class's records.  Any pointer may be
+ * NULL.
+ */
+gift_status gift_profile_collect(int32_t prof_class, int64_t *launches, double *total_ms,
+                                 double *max_ms, double *bytes);
+
+/* ------------------------------------------------------------------------
+ * Misc.
+ * ----------------------------------------------------------------------*/
+
+const char *gift_status_string(gift_status status);
+
+/* Description of the last error raised on the calling host thread ("" if
+ * none).  The pointer is valid until the next library call on that thread. */
+const char *gift_last_error(void);
+
+/* Library and ABI version: returns GIFT_ABI_VERSION. */
+int32_t gift_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GIFT_H */

@@ -1,0 +1,118 @@
+"""ctypes declarations of the C ABI in ``include/gift.h``.
+
+Loading fails loudly when ``libgift.so`` has not been built: there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("GIFT_LIBRARY", os.path.join(HERE, "libgift.so"))
+
+GIFT_OK, GIFT_EINVAL, GIFT_ENOMEM, GIFT_EDEVICE, GIFT_EUNSUPPORTED, GIFT_EBUSY = range(6)
+GIFT_F32, GIFT_F64, GIFT_BF16, GIFT_F16 = range(4)
+GIFT_W_INV_M1, GIFT_W_TWO_OVER_M = range(2)
+GIFT_MEM_HOST, GIFT_MEM_DEVICE = range(2)
+GIFT_PROF_SPMM, GIFT_PROF_SPMM_FINAL, GIFT_PROF_BUILD = range(3)
+
+
+class GraphDesc(C.Structure):
+    _fields_ = [
+        ("num_cells", C.c_int64),
+        ("num_nets", C.c_int64),
+        ("net_ptr", C.c_void_p),
+        ("pin_cell", C.c_void_p),
+        ("mem_space", C.c_int32),
+        ("weight_model", C.c_int32),
+        ("star_threshold", C.c_int64),
+        ("storage", C.c_int32),
+        ("num_sigmas", C.c_int32),
+        ("sigmas", C.c_void_p),
+    ]
+
+
+class Term(C.Structure):
+    _fields_ = [("sigma", C.c_double), ("order", C.c_int32), ("reserved", C.c_int32),
+                ("alpha", C.c_double)]
+
+
+class GraphInfo(C.Structure):
+    _fields_ = [
+        ("num_cells", C.c_int64),
+        ("num_virtual", C.c_int64),
+        ("num_rows", C.c_int64),
+        ("nnz", C.c_int64),
+        ("bytes_resident", C.c_int64),
+        ("storage", C.c_int32),
+        ("num_sigmas", C.c_int32),
+    ]
+
+
+class BatchIO(C.Structure):
+    _fields_ = [("x_in", C.c_void_p), ("ld_in", C.c_int64), ("y_out", C.c_void_p),
+                ("ld_out", C.c_int64), ("fixed_mask", C.c_void_p)]
+
+
+class GiftError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        self.status = status
+        super().__init__(f"{where}: status {status}: {message}")
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "gift_build_graph": (C.c_int, [C.POINTER(GraphDesc), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "gift_filter_placement": (C.c_int, [C.c_void_p, C.POINTER(Term), C.c_int32, C.c_void_p,
+                                        C.c_int32, C.c_int64, C.c_int32, C.c_void_p, C.c_int64,
+                                        C.c_int32, C.c_void_p, C.c_void_p]),
+    "gift_graph_add_sigma": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p]),
+    "gift_graph_get_info": (C.c_int, [C.c_void_p, C.POINTER(GraphInfo)]),
+    "gift_graph_export": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.c_void_p]),
+    "gift_graph_export_normalised": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p,
+                                               C.c_void_p]),
+    "gift_destroy_graph": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "gift_batch_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(Term), C.c_int32,
+                                    C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                                    C.POINTER(C.c_void_p)]),
+    "gift_batch_run": (C.c_int, [C.c_void_p, C.POINTER(BatchIO), C.c_void_p]),
+    "gift_batch_schedule": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_int64)]),
+    "gift_batch_destroy": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "gift_profile_enable": (C.c_int, [C.c_int32]),
+    "gift_profile_collect": (C.c_int, [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                       C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "gift_status_string": (C.c_char_p, [C.c_int]),
+    "gift_last_error": (C.c_char_p, []),
+    "gift_abi_version": (C.c_int32, []),
+}
+
+
+def lib():
+    """The loaded library (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; g.build()'` "
+            "or `python paper_2502_17632_amd/build_lib.py` first")
+    L = C.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(L, name, None)
+        if fn is None:
+            continue
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def check(status: int, where: str):
+    if status != GIFT_OK:
+        msg = lib().gift_last_error().decode(errors="replace")
+        raise GiftError(status, where, msg)

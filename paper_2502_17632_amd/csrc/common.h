@@ -1,0 +1,225 @@
+// Internal declarations shared by the library's HIP sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "gift.h"
+
+namespace gift {
+
+// ---------------------------------------------------------------------------
+// Errors: every entry point returns a status and records a message per host
+// thread.
+// ---------------------------------------------------------------------------
+gift_status set_error(gift_status s, const char *fmt, ...);
+void clear_error();
+
+#define GIFT_HIP(call)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return ::gift::set_error(e_ == hipErrorOutOfMemory ? GIFT_ENOMEM : GIFT_EDEVICE, \
+                               "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                               __FILE__, __LINE__);                                \
+  } while (0)
+
+#define GIFT_TRY(expr)                  \
+  do {                                  \
+    gift_status s_ = (expr);            \
+    if (s_ != GIFT_OK) return s_;       \
+  } while (0)
+
+// Checks the launch that was just enqueued.
+gift_status check_launch(const char *what);
+
+// Brackets the launches made while it is alive with profiler events (when
+// the profiler is enabled); `bytes` is their algorithmic traffic.
+class ProfScope {
+ public:
+  ProfScope(hipStream_t s, int cls, double bytes);
+  ~ProfScope();
+  ProfScope(const ProfScope &) = delete;
+  ProfScope &operator=(const ProfScope &) = delete;
+
+ private:
+  int idx_;
+  hipStream_t stream_;
+};
+
+// ---------------------------------------------------------------------------
+// Device memory: stream-ordered allocations (hipMallocAsync / hipFreeAsync),
+// so that building, filtering and releasing graphs on different streams does
+// not serialise the device.
+// ---------------------------------------------------------------------------
+gift_status dev_alloc(void **p, size_t bytes, hipStream_t s, const char *what);
+void dev_free(void *p, hipStream_t s);
+
+// RAII holder for build/filter scratch, released in stream order.
+struct Scratch {
+  hipStream_t stream;
+  std::vector<void *> ptrs;
+  explicit Scratch(hipStream_t s) : stream(s) {}
+  ~Scratch() {
+    for (void *p : ptrs) dev_free(p, stream);
+  }
+  template <typename T>
+  gift_status get(T **p, size_t count, const char *what) {
+    void *v = nullptr;
+    gift_status st = dev_alloc(&v, count * sizeof(T) + 16, stream, what);
+    if (st != GIFT_OK) return st;
+    ptrs.push_back(v);
+    *p = static_cast<T *>(v);
+    return GIFT_OK;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Resident graph.
+// ---------------------------------------------------------------------------
+struct SigmaBlock {
+  double sigma;
+  void *val;  // storage type [nnz]: a_ij = (w_ij s_i) s_j
+  void *diag; // accumulation type [R]: (sigma s_i) s_i
+};
+
+}  // namespace gift
+
+struct gift_graph {
+  int64_t num_cells = 0;    // N
+  int64_t num_virtual = 0;  // V
+  int64_t num_rows = 0;     // R
+  int64_t nnz = 0;
+  int64_t nnz_cells = 0;     // entries in rows [0, N)
+  int32_t storage = GIFT_F32;
+  int32_t weight_model = GIFT_W_INV_M1;
+  int64_t star_threshold = 0;
+  int32_t *row_ptr = nullptr;  // int32[R+1]
+  int32_t *col = nullptr;      // int32[nnz]
+  double *w = nullptr;         // float64[nnz]
+  double *deg = nullptr;       // float64[R]
+  std::vector<gift::SigmaBlock> sig;
+  int64_t bytes = 0;
+  int device = 0;
+  // Row-split schedule of the SpMM (chosen at build time).
+  int32_t group_cells = 4;    // lanes per row for rows [0, N)
+  int32_t group_virtual = 16; // lanes per row for rows [N, R)
+};
+
+namespace gift {
+
+inline size_t dtype_size(int32_t d) {
+  switch (d) {
+    case GIFT_F32: return 4;
+    case GIFT_F64: return 8;
+    case GIFT_BF16: return 2;
+    case GIFT_F16: return 2;
+  }
+  return 0;
+}
+inline bool dtype_valid(int32_t d) { return d >= GIFT_F32 && d <= GIFT_F16; }
+// Accumulation type of a storage type: float64 for F64, float32 otherwise.
+inline size_t accum_size(int32_t storage) { return storage == GIFT_F64 ? 8 : 4; }
+
+const SigmaBlock *find_sigma(const gift_graph *g, double sigma);
+gift_status prepare_sigma(gift_graph *g, double sigma, hipStream_t s);
+
+// Exclusive prefix sum: out[0..n] with out[n] = total (int64 output).
+gift_status scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Storage types.  bf16 and f16 are stored as raw 16-bit patterns; values are
+// rounded to nearest-even when stored.
+// ---------------------------------------------------------------------------
+struct bf16 {
+  uint16_t bits;
+};
+struct f16 {
+  uint16_t bits;
+};
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) {
+  return __uint_as_float(static_cast<uint32_t>(h) << 16);
+}
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return static_cast<uint16_t>((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+__device__ __forceinline__ float f16_to_f32(uint16_t h) {
+  _Float16 v;
+  __builtin_memcpy(&v, &h, 2);
+  return static_cast<float>(v);
+}
+__device__ __forceinline__ uint16_t f32_to_f16(float f) {
+  _Float16 v = static_cast<_Float16>(f);
+  uint16_t h;
+  __builtin_memcpy(&h, &v, 2);
+  return h;
+}
+// float64 -> float32 rounded to odd: exact results stay exact, inexact ones
+// get their last bit set.  A second rounding to a format with at least two
+// fewer significand bits (bf16, f16) is then correctly rounded.
+__device__ __forceinline__ float f64_to_f32_odd(double d) {
+  float t = __double2float_rz(d);
+  if (static_cast<double>(t) != d) t = __uint_as_float(__float_as_uint(t) | 1u);
+  return t;
+}
+
+template <int D>
+struct Store;
+template <>
+struct Store<GIFT_F32> {
+  using T = float;
+  using A = float;
+  static __device__ __forceinline__ A load(T v) { return v; }
+  static __device__ __forceinline__ T from_acc(A a) { return a; }
+  static __device__ __forceinline__ T from_f64(double d) { return static_cast<float>(d); }
+};
+template <>
+struct Store<GIFT_F64> {
+  using T = double;
+  using A = double;
+  static __device__ __forceinline__ A load(T v) { return v; }
+  static __device__ __forceinline__ T from_acc(A a) { return a; }
+  static __device__ __forceinline__ T from_f64(double d) { return d; }
+};
+template <>
+struct Store<GIFT_BF16> {
+  using T = uint16_t;
+  using A = float;
+  static __device__ __forceinline__ A load(T v) { return bf16_to_f32(v); }
+  static __device__ __forceinline__ T from_acc(A a) { return f32_to_bf16(a); }
+  static __device__ __forceinline__ T from_f64(double d) { return f32_to_bf16(f64_to_f32_odd(d)); }
+};
+template <>
+struct Store<GIFT_F16> {
+  using T = uint16_t;
+  using A = float;
+  static __device__ __forceinline__ A load(T v) { return f16_to_f32(v); }
+  static __device__ __forceinline__ T from_acc(A a) { return f32_to_f16(a); }
+  static __device__ __forceinline__ T from_f64(double d) { return f32_to_f16(f64_to_f32_odd(d)); }
+};
+
+// Blocks are dispatched round-robin over the 8 XCDs.  Remap so that every XCD
+// works on one contiguous range of logical blocks (and so of rows): the signal
+// rows a block gathers are then mostly in its own XCD's L2.
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t n) {
+  const uint32_t kXcd = 8;
+  uint32_t x = b % kXcd, i = b / kXcd;
+  uint32_t q = n / kXcd, r = n % kXcd;
+  return x * q + (x < r ? x : r) + i;
+}
+
+inline unsigned grid_for(int64_t threads, int block = 256) {
+  int64_t b = (threads + block - 1) / block;
+  if (b < 1) b = 1;
+  return static_cast<unsigned>(b);
+}
+
+}  // namespace gift

@@ -1,0 +1,394 @@
+// Multi-order graph filter g' = sum_t alpha_t A~_{sigma_t}^{k_t} g
+// (Section 3.2.1, eq. proposed_filter; the powers are the repeated sparse
+// products of the complexity paragraph in Section 3.2.2).
+//
+// Per distinct sigma the signal goes through k_max SpMM passes
+//     x_k[i] = sum_j a_ij x_{k-1}[j] + diag_i x_{k-1}[i]
+// (storage-type values and signals, float32 or float64 accumulation).  The
+// last pass of the last sigma also forms the float64 combine of all terms, in
+// term order, and writes the caller's output; iterates needed by earlier terms
+// are kept in their own buffers.
+//
+// The pass is bound by HBM bandwidth (about 0.4 flop per byte): it streams
+// row_ptr, col and the values once and gathers signal rows.  A group of G
+// lanes works on one row (G per row segment: cell rows are short, star rows
+// long), the lanes of a group read consecutive entries, and the group's
+// partial sums are combined with cross-lane shuffles.  Blocks are remapped so
+// each XCD works on one contiguous range of rows.
+#include <cmath>
+#include <cstring>
+
+#include "common.h"
+#include "devutil.h"
+
+namespace gift {
+
+constexpr int kMaxTerms = 64;
+
+struct PassArgs {
+  const int32_t *row_ptr;
+  const int32_t *col;
+  const void *val;
+  const void *diag;
+  const void *x;
+  void *y;
+  int64_t rows_a;    // rows [0, rows_a) use lanes_a lanes per row
+  int64_t rows_end;  // rows [rows_a, rows_end) use lanes_b lanes per row
+  int32_t lanes_a, lanes_b;
+  uint32_t blocks_a; // blocks covering segment a
+};
+
+struct FinalArgs {
+  int32_t num_terms;
+  int32_t in_dtype, out_dtype;
+  int32_t col0;  // first column of this chunk in the caller's matrices
+  const void *src[kMaxTerms];  // saved iterate of each term; NULL = this pass
+  double alpha[kMaxTerms];
+  const void *x_in;
+  int64_t ld_in;
+  void *y_out;
+  int64_t ld_out;
+  const uint8_t *fixed;
+};
+
+template <typename T, int C>
+struct SigRow {
+  static constexpr int kBytes = static_cast<int>(sizeof(T)) * C;
+  static constexpr int kAlign = kBytes >= 16 ? 16 : kBytes;
+  struct alignas(kAlign) V {
+    T v[C];
+  };
+};
+
+template <typename T, int C>
+__device__ __forceinline__ typename SigRow<T, C>::V load_row(const T *__restrict__ x, int64_t r) {
+  return reinterpret_cast<const typename SigRow<T, C>::V *>(x)[r];
+}
+
+__device__ __forceinline__ double load_in(const void *p, int32_t dt, int64_t i) {
+  return dt == GIFT_F64 ? static_cast<const double *>(p)[i]
+                        : static_cast<double>(static_cast<const float *>(p)[i]);
+}
+
+template <int D, int C, bool kFinal>
+__global__ __launch_bounds__(kBlock) void k_spmm(PassArgs p, FinalArgs f) {
+  using S = Store<D>;
+  using T = typename S::T;
+  using A = typename S::A;
+  const uint32_t blk = xcd_remap(blockIdx.x, gridDim.x);
+  int64_t row;
+  int G;
+  if (blk < p.blocks_a) {
+    G = p.lanes_a;
+    row = static_cast<int64_t>(blk) * (kBlock / G) + threadIdx.x / G;
+    if (row >= p.rows_a) row = -1;
+  } else {
+    G = p.lanes_b;
+    row = p.rows_a + static_cast<int64_t>(blk - p.blocks_a) * (kBlock / G) + threadIdx.x / G;
+    if (row >= p.rows_end) row = -1;
+  }
+  const int lane = threadIdx.x & (G - 1);
+  const T *__restrict__ x = static_cast<const T *>(p.x);
+  const T *__restrict__ val = static_cast<const T *>(p.val);
+  const int32_t *__restrict__ col = p.col;
+  A acc[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) acc[c] = 0;
+  if (row >= 0) {
+    const int32_t p0 = p.row_ptr[row], p1 = p.row_ptr[row + 1];
+    int32_t q = p0 + lane;
+    for (; q + G < p1; q += 2 * G) {
+      const int32_t j0 = col[q], j1 = col[q + G];
+      const A v0 = S::load(val[q]), v1 = S::load(val[q + G]);
+      const auto x0 = load_row<T, C>(x, j0);
+      const auto x1 = load_row<T, C>(x, j1);
+#pragma unroll
+      for (int c = 0; c < C; ++c) acc[c] += v0 * S::load(x0.v[c]);
+#pragma unroll
+      for (int c = 0; c < C; ++c) acc[c] += v1 * S::load(x1.v[c]);
+    }
+    if (q < p1) {
+      const int32_t j0 = col[q];
+      const A v0 = S::load(val[q]);
+      const auto x0 = load_row<T, C>(x, j0);
+#pragma unroll
+      for (int c = 0; c < C; ++c) acc[c] += v0 * S::load(x0.v[c]);
+    }
+  }
+  for (int off = G >> 1; off > 0; off >>= 1) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] += __shfl_xor(acc[c], off);
+  }
+  if (row < 0 || lane != 0) return;
+  const A dg = static_cast<const A *>(p.diag)[row];
+  const auto xi = load_row<T, C>(x, row);
+#pragma unroll
+  for (int c = 0; c < C; ++c) acc[c] = acc[c] + dg * S::load(xi.v[c]);
+  if constexpr (!kFinal) {
+    typename SigRow<T, C>::V out;
+#pragma unroll
+    for (int c = 0; c < C; ++c) out.v[c] = S::from_acc(acc[c]);
+    reinterpret_cast<typename SigRow<T, C>::V *>(p.y)[row] = out;
+  } else {
+    const bool fixed = f.fixed && f.fixed[row];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      double s = 0.0;
+      if (fixed) {
+        s = load_in(f.x_in, f.in_dtype, row * f.ld_in + f.col0 + c);
+      } else {
+        for (int t = 0; t < f.num_terms; ++t) {
+          const T *src = static_cast<const T *>(f.src[t]);
+          double v = src ? static_cast<double>(S::load(src[row * C + c]))
+                         : static_cast<double>(acc[c]);
+          s = s + f.alpha[t] * v;
+        }
+      }
+      const int64_t o = row * f.ld_out + f.col0 + c;
+      if (f.out_dtype == GIFT_F64) static_cast<double *>(f.y_out)[o] = s;
+      else static_cast<float *>(f.y_out)[o] = static_cast<float>(s);
+    }
+  }
+}
+
+// Rows [0, N): the caller's signal, rounded to the storage type.
+template <int D, int C>
+__global__ void k_prep_cells(const void *x_in, int64_t ld_in, int32_t in_dtype, int32_t col0,
+                             int64_t N, typename Store<D>::T *x0) {
+  int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= N * C) return;
+  int64_t r = i / C;
+  int c = static_cast<int>(i - r * C);
+  x0[i] = Store<D>::from_f64(load_in(x_in, in_dtype, r * ld_in + col0 + c));
+}
+
+// Star rows [N, R): the mean of the net's cells (float64 sum), one wave each.
+template <int D, int C>
+__global__ __launch_bounds__(kBlock) void k_prep_stars(const int32_t *row_ptr,
+                                                       const int32_t *col, const void *x_in,
+                                                       int64_t ld_in, int32_t in_dtype,
+                                                       int32_t col0, int64_t N, int64_t V,
+                                                       typename Store<D>::T *x0) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t waves = static_cast<int64_t>(gridDim.x) * (kBlock / kWave);
+  for (int64_t v = static_cast<int64_t>(blockIdx.x) * (kBlock / kWave) + threadIdx.x / kWave;
+       v < V; v += waves) {
+    const int64_t r = N + v;
+    const int32_t p0 = row_ptr[r], p1 = row_ptr[r + 1];
+    double s[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) s[c] = 0.0;
+    for (int32_t q = p0 + lane; q < p1; q += kWave) {
+      const int64_t j = col[q];
+#pragma unroll
+      for (int c = 0; c < C; ++c) s[c] += load_in(x_in, in_dtype, j * ld_in + col0 + c);
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+      for (int off = kWave / 2; off > 0; off >>= 1) s[c] += __shfl_xor(s[c], off);
+    if (lane == 0) {
+      const double m = static_cast<double>(p1 - p0);
+#pragma unroll
+      for (int c = 0; c < C; ++c) x0[r * C + c] = Store<D>::from_f64(m > 0 ? s[c] / m : 0.0);
+    }
+  }
+}
+
+namespace {
+
+struct Group {
+  double sigma;
+  int32_t kmax;
+  const SigmaBlock *blk;
+};
+
+// Algorithmic bytes of one SpMM pass: row_ptr, col and values of the rows it
+// covers, their diagonal, every signal row read once, the iterate written.
+// The last pass covers the cell rows only, reads the saved iterates of the
+// other terms and writes the output instead.
+template <int D, int C>
+double pass_bytes(const gift_graph *g, bool fin, int32_t nt, int32_t out_dt) {
+  const double bt = sizeof(typename Store<D>::T), ba = sizeof(typename Store<D>::A);
+  const double rows = static_cast<double>(fin ? g->num_cells : g->num_rows);
+  const double nnz = static_cast<double>(fin ? g->nnz_cells : g->nnz);
+  const double R = static_cast<double>(g->num_rows);
+  double b = 4.0 * (rows + 1) + (4.0 + bt) * nnz + ba * rows + bt * C * R;
+  if (!fin) return b + bt * C * rows;
+  return b + (nt - 1) * bt * C * rows + (out_dt == GIFT_F64 ? 8.0 : 4.0) * C * rows;
+}
+
+template <int D, int C>
+gift_status run_chunk(const gift_graph *g, const std::vector<Group> &groups,
+                      const gift_term *terms, int32_t nt, const void *x_in, int64_t ld_in,
+                      int32_t in_dt, void *y_out, int64_t ld_out, int32_t out_dt,
+                      const uint8_t *fixed, int32_t col0, hipStream_t st) {
+  using T = typename Store<D>::T;
+  const int64_t N = g->num_cells, V = g->num_virtual, R = g->num_rows;
+  Scratch sc(st);
+  T *x0 = nullptr, *ping = nullptr, *pong = nullptr;
+  GIFT_TRY(sc.get(&x0, R * C, "signal x0"));
+  GIFT_TRY(sc.get(&ping, R * C, "signal ping"));
+  GIFT_TRY(sc.get(&pong, R * C, "signal pong"));
+  // saved iterate for every term that is not the very last pass
+  std::vector<T *> saved(nt, nullptr);
+  const Group &last = groups.back();
+  for (int32_t t = 0; t < nt; ++t) {
+    bool is_final = terms[t].sigma == last.sigma && terms[t].order == last.kmax;
+    if (is_final) continue;
+    for (int32_t u = 0; u < t; ++u)
+      if (terms[u].sigma == terms[t].sigma && terms[u].order == terms[t].order) saved[t] = saved[u];
+    if (!saved[t]) GIFT_TRY(sc.get(&saved[t], R * C, "saved iterate"));
+  }
+
+  k_prep_cells<D, C><<<grid_for(N * C), kBlock, 0, st>>>(x_in, ld_in, in_dt, col0, N, x0);
+  GIFT_TRY(check_launch("k_prep_cells"));
+  if (V > 0) {
+    k_prep_stars<D, C><<<grid_for(V * kWave), kBlock, 0, st>>>(g->row_ptr, g->col, x_in, ld_in,
+                                                                in_dt, col0, N, V, x0);
+    GIFT_TRY(check_launch("k_prep_stars"));
+  }
+
+  FinalArgs fa{};
+  fa.num_terms = nt;
+  fa.in_dtype = in_dt;
+  fa.out_dtype = out_dt;
+  fa.col0 = col0;
+  fa.x_in = x_in;
+  fa.ld_in = ld_in;
+  fa.y_out = y_out;
+  fa.ld_out = ld_out;
+  fa.fixed = fixed;
+  for (int32_t t = 0; t < nt; ++t) {
+    fa.src[t] = saved[t];
+    fa.alpha[t] = terms[t].alpha;
+  }
+
+  const int32_t ga = g->group_cells, gb = g->group_virtual;
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    const Group &grp = groups[gi];
+    const T *cur = x0;
+    for (int32_t k = 1; k <= grp.kmax; ++k) {
+      const bool fin = gi + 1 == groups.size() && k == grp.kmax;
+      T *dst = nullptr;
+      if (!fin) {
+        for (int32_t t = 0; t < nt; ++t)
+          if (terms[t].sigma == grp.sigma && terms[t].order == k) dst = saved[t];
+        if (!dst) dst = (cur == ping) ? pong : ping;
+      }
+      PassArgs pa{};
+      pa.row_ptr = g->row_ptr;
+      pa.col = g->col;
+      pa.val = grp.blk->val;
+      pa.diag = grp.blk->diag;
+      pa.x = cur;
+      pa.y = dst;
+      pa.rows_a = N;
+      pa.rows_end = fin ? N : R;
+      pa.lanes_a = ga;
+      pa.lanes_b = gb;
+      pa.blocks_a = static_cast<uint32_t>((N + (kBlock / ga) - 1) / (kBlock / ga));
+      int64_t blocks_b = (pa.rows_end - N + (kBlock / gb) - 1) / (kBlock / gb);
+      unsigned grid = static_cast<unsigned>(pa.blocks_a + blocks_b);
+      if (grid == 0) continue;
+      {
+        ProfScope ps(st, fin ? GIFT_PROF_SPMM_FINAL : GIFT_PROF_SPMM,
+                     pass_bytes<D, C>(g, fin, nt, out_dt));
+        if (fin) k_spmm<D, C, true><<<grid, kBlock, 0, st>>>(pa, fa);
+        else k_spmm<D, C, false><<<grid, kBlock, 0, st>>>(pa, fa);
+      }
+      GIFT_TRY(check_launch("k_spmm"));
+      cur = dst;
+    }
+  }
+  return GIFT_OK;
+}
+
+template <int D>
+gift_status run_chunk_c(int C, const gift_graph *g, const std::vector<Group> &groups,
+                        const gift_term *terms, int32_t nt, const void *x_in, int64_t ld_in,
+                        int32_t in_dt, void *y_out, int64_t ld_out, int32_t out_dt,
+                        const uint8_t *fixed, int32_t col0, hipStream_t st) {
+  switch (C) {
+    case 1: return run_chunk<D, 1>(g, groups, terms, nt, x_in, ld_in, in_dt, y_out, ld_out, out_dt, fixed, col0, st);
+    case 2: return run_chunk<D, 2>(g, groups, terms, nt, x_in, ld_in, in_dt, y_out, ld_out, out_dt, fixed, col0, st);
+    case 4: return run_chunk<D, 4>(g, groups, terms, nt, x_in, ld_in, in_dt, y_out, ld_out, out_dt, fixed, col0, st);
+    case 8: return run_chunk<D, 8>(g, groups, terms, nt, x_in, ld_in, in_dt, y_out, ld_out, out_dt, fixed, col0, st);
+    case 16: return run_chunk<D, 16>(g, groups, terms, nt, x_in, ld_in, in_dt, y_out, ld_out, out_dt, fixed, col0, st);
+  }
+  return set_error(GIFT_EUNSUPPORTED, "column chunk %d", C);
+}
+
+}  // namespace
+
+// Terms grouped by distinct sigma (ascending), each with its highest order.
+gift_status plan_groups(const gift_graph *g, const gift_term *terms, int32_t nt,
+                        std::vector<Group> *out);
+
+gift_status plan_groups(const gift_graph *g, const gift_term *terms, int32_t nt,
+                        std::vector<Group> *out) {
+  out->clear();
+  for (int32_t t = 0; t < nt; ++t) {
+    const gift_term &tm = terms[t];
+    if (!(tm.sigma >= 0.0) || !std::isfinite(tm.sigma))
+      return set_error(GIFT_EINVAL, "term %d: sigma %g", t, tm.sigma);
+    if (tm.order < 1) return set_error(GIFT_EINVAL, "term %d: order %d < 1", t, tm.order);
+    if (!std::isfinite(tm.alpha)) return set_error(GIFT_EINVAL, "term %d: alpha not finite", t);
+    if (tm.reserved != 0) return set_error(GIFT_EINVAL, "term %d: reserved field not 0", t);
+    const SigmaBlock *b = find_sigma(g, tm.sigma);
+    if (!b)
+      return set_error(GIFT_EINVAL, "term %d: sigma %g was not prepared for this graph", t,
+                       tm.sigma);
+    bool found = false;
+    for (Group &gr : *out)
+      if (gr.sigma == tm.sigma) {
+        if (tm.order > gr.kmax) gr.kmax = tm.order;
+        found = true;
+      }
+    if (!found) out->push_back(Group{tm.sigma, tm.order, b});
+  }
+  for (size_t i = 1; i < out->size(); ++i)
+    for (size_t j = i; j > 0 && (*out)[j].sigma < (*out)[j - 1].sigma; --j)
+      std::swap((*out)[j], (*out)[j - 1]);
+  return GIFT_OK;
+}
+
+}  // namespace gift
+
+using namespace gift;
+
+extern "C" gift_status gift_filter_placement(const gift_graph *g, const gift_term *terms,
+                                             int32_t nt, const void *x_in, int32_t num_cols,
+                                             int64_t ld_in, int32_t in_dt, void *y_out,
+                                             int64_t ld_out, int32_t out_dt,
+                                             const uint8_t *fixed, void *stream) {
+  clear_error();
+  if (!g || !terms) return set_error(GIFT_EINVAL, "gift_filter_placement: NULL graph or terms");
+  if (nt < 1 || nt > kMaxTerms) return set_error(GIFT_EINVAL, "num_terms %d not in [1, 64]", nt);
+  if (num_cols < 1) return set_error(GIFT_EINVAL, "num_cols %d < 1", num_cols);
+  if (ld_in < num_cols || ld_out < num_cols)
+    return set_error(GIFT_EINVAL, "leading dimension smaller than num_cols");
+  if (in_dt != GIFT_F32 && in_dt != GIFT_F64)
+    return set_error(GIFT_EUNSUPPORTED, "in_dtype must be F32 or F64");
+  if (out_dt != GIFT_F32 && out_dt != GIFT_F64)
+    return set_error(GIFT_EUNSUPPORTED, "out_dtype must be F32 or F64");
+  std::vector<gift::Group> groups;
+  GIFT_TRY(plan_groups(g, terms, nt, &groups));
+  if (g->num_cells == 0) return GIFT_OK;
+  if (!x_in || !y_out) return set_error(GIFT_EINVAL, "x_in / y_out is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int32_t col0 = 0;
+  while (col0 < num_cols) {
+    int rem = num_cols - col0;
+    int C = rem >= 16 ? 16 : rem >= 8 ? 8 : rem >= 4 ? 4 : rem >= 2 ? 2 : 1;
+    gift_status s = GIFT_OK;
+    switch (g->storage) {
+      case GIFT_F32: s = run_chunk_c<GIFT_F32>(C, g, groups, terms, nt, x_in, ld_in, in_dt, y_out, ld_out, out_dt, fixed, col0, st); break;
+      case GIFT_F64: s = run_chunk_c<GIFT_F64>(C, g, groups, terms, nt, x_in, ld_in, in_dt, y_out, ld_out, out_dt, fixed, col0, st); break;
+      case GIFT_BF16: s = run_chunk_c<GIFT_BF16>(C, g, groups, terms, nt, x_in, ld_in, in_dt, y_out, ld_out, out_dt, fixed, col0, st); break;
+      case GIFT_F16: s = run_chunk_c<GIFT_F16>(C, g, groups, terms, nt, x_in, ld_in, in_dt, y_out, ld_out, out_dt, fixed, col0, st); break;
+    }
+    if (s != GIFT_OK) return s;
+    col0 += C;
+  }
+  return GIFT_OK;
+}

@@ -1,0 +1,80 @@
+// Device-wide exclusive prefix sum (reduce / scan-of-tile-sums / scan), used
+// for CSR row offsets and per-net output offsets.
+#include "common.h"
+#include "devutil.h"
+
+namespace gift {
+namespace {
+
+constexpr int kItems = 8;
+constexpr int64_t kTile = static_cast<int64_t>(kBlock) * kItems;
+
+template <typename In>
+__global__ __launch_bounds__(kBlock) void k_tile_sums(const In *__restrict__ in, int64_t n,
+                                                      int64_t *__restrict__ sums) {
+  __shared__ int64_t tmp[kBlock / kWave];
+  int64_t base = static_cast<int64_t>(blockIdx.x) * kTile;
+  int64_t v = 0;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    int64_t i = base + k * kBlock + threadIdx.x;
+    if (i < n) v += static_cast<int64_t>(in[i]);
+  }
+  int64_t t = block_sum<int64_t>(v, tmp);
+  if (threadIdx.x == 0) sums[blockIdx.x] = t;
+}
+
+// out[i] = offs[tile] + exclusive prefix within the tile; the last tile also
+// writes out[n] (the grand total).
+template <typename In>
+__global__ __launch_bounds__(kBlock) void k_tile_scan(const In *__restrict__ in, int64_t n,
+                                                      const int64_t *__restrict__ offs,
+                                                      int64_t *__restrict__ out) {
+  __shared__ int64_t tmp[kBlock / kWave];
+  int64_t base = static_cast<int64_t>(blockIdx.x) * kTile + static_cast<int64_t>(threadIdx.x) * kItems;
+  int64_t v[kItems];
+  int64_t mine = 0;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    int64_t i = base + k;
+    v[k] = i < n ? static_cast<int64_t>(in[i]) : 0;
+    mine += v[k];
+  }
+  int64_t total;
+  int64_t run = block_excl_scan<int64_t>(mine, &total, tmp);
+  int64_t off = offs ? offs[blockIdx.x] : 0;
+  run += off;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    int64_t i = base + k;
+    if (i < n) out[i] = run;
+    run += v[k];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = off + total;
+}
+
+template <typename In>
+gift_status scan_impl(const In *in, int64_t *out, int64_t n, hipStream_t s) {
+  if (n <= kTile) {
+    k_tile_scan<In><<<1, kBlock, 0, s>>>(in, n, nullptr, out);
+    return check_launch("k_tile_scan");
+  }
+  int64_t nb = (n + kTile - 1) / kTile;
+  Scratch sc(s);
+  int64_t *sums = nullptr, *offs = nullptr;
+  GIFT_TRY(sc.get(&sums, nb, "scan tile sums"));
+  GIFT_TRY(sc.get(&offs, nb + 1, "scan tile offsets"));
+  k_tile_sums<In><<<static_cast<unsigned>(nb), kBlock, 0, s>>>(in, n, sums);
+  GIFT_TRY(check_launch("k_tile_sums"));
+  GIFT_TRY(scan_impl<int64_t>(sums, offs, nb, s));
+  k_tile_scan<In><<<static_cast<unsigned>(nb), kBlock, 0, s>>>(in, n, offs, out);
+  return check_launch("k_tile_scan");
+}
+
+}  // namespace
+
+gift_status scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, hipStream_t s) {
+  return scan_impl<int32_t>(in, out, n, s);
+}
+
+}  // namespace gift

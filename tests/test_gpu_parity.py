@@ -1,0 +1,219 @@
+"""Device path vs the CPU oracle on the same seeded inputs (needs a GPU)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2502_17632_amd import workload as W
+
+from parity import TOL, assert_close, check_normalised, check_structure, log, run_pair
+
+pytestmark = pytest.mark.gpu
+
+EQ4 = ([4.0] * 4, [1, 2, 4, 8], [0.25] * 4)
+EQ5 = ([4.0] * 5, [1, 2, 4, 8, 16], [0.2] * 5)
+PAPER = (W.PAPER_DEFAULT.sigma, W.PAPER_DEFAULT.order, W.PAPER_DEFAULT.alpha)
+
+
+def handmade(nets, n):
+    net_ptr = np.zeros(len(nets) + 1, dtype=np.int64)
+    net_ptr[1:] = np.cumsum([len(p) for p in nets])
+    pins = np.array([c for p in nets for c in p], dtype=np.int32)
+    return W.Netlist(n, net_ptr, pins, np.zeros(n, dtype=np.uint8), "handmade")
+
+
+@pytest.fixture(scope="module")
+def medium():
+    return W.medium()
+
+
+@pytest.fixture(scope="module")
+def medium_oracle(medium):
+    return O.build_netlist(medium, star_threshold=16)
+
+
+def test_tiny_f64_equal_weights():
+    nl = W.tiny()
+    x = W.make_signal(nl)
+    y, ref, g, og = run_pair(nl, x, EQ4, storage="f64", label="tiny f64")
+    check_normalised(g, og, 4.0, "f64")
+    assert_close(y, ref, "f64", "tiny f64")
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16", "f16"])
+def test_tiny_paper_filter(storage):
+    nl = W.tiny(seed=1)
+    x = W.make_signal(nl, seed=1)
+    y, ref, g, og = run_pair(nl, x, PAPER, storage=storage, label=f"tiny paper {storage}")
+    for s in (2.0, 4.0):
+        check_normalised(g, og, s, storage)
+    assert_close(y, ref, storage, f"tiny paper {storage}")
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16", "f16"])
+def test_medium(medium, medium_oracle, storage):
+    x = W.make_signal(medium)
+    y, ref, g, og = run_pair(medium, x, EQ4, storage=storage, star_threshold=16,
+                             og=medium_oracle, label=f"medium {storage}")
+    check_normalised(g, og, 4.0, storage)
+    assert_close(y, ref, storage, f"medium {storage}")
+
+
+def test_medium_two_over_m_paper_terms(medium):
+    x = W.make_signal(medium, seed=3)
+    y, ref, g, og = run_pair(medium, x, PAPER, storage="f32", star_threshold=16,
+                             weight_model="two_over_m", label="medium 2/M paper")
+    assert_close(y, ref, "f32", "medium 2/M paper")
+
+
+def test_medium_all_cliques(medium):
+    # T = 0: nets of up to 1000 pins expand as cliques (long rows, big sorts)
+    x = W.make_signal(medium, seed=4)
+    y, ref, g, og = run_pair(medium, x, EQ4, storage="f32", star_threshold=0,
+                             label="medium cliques")
+    assert_close(y, ref, "f32", "medium cliques")
+
+
+def test_sort_tiers_and_long_rows():
+    # nets of 3, 40 (wave tier), 500 (LDS tier) and 9000 (global merge tier)
+    # pins, with repeated pins; cell 0 on 5000 two-pin nets (row sorted by the
+    # global merge tier), cell 1 on 300 (LDS tier), cell 2 on 40 (wave tier)
+    rng = np.random.default_rng(11)
+    n = 20_000
+    nets = [[5, 6, 7]]
+    for m in (40, 500, 9000):
+        cells = list(rng.choice(np.arange(10, n), size=m, replace=False))
+        cells += cells[:3]  # repeated pins
+        rng.shuffle(cells)
+        nets.append(cells)
+    for hub, count in ((0, 5000), (1, 300), (2, 40)):
+        for c in rng.choice(np.arange(10, n), size=count, replace=False):
+            nets.append([hub, int(c)] if rng.random() < 0.5 else [int(c), hub])
+    nl = handmade(nets, n)
+    x = rng.normal(500, 50, size=(n, 2))
+    for thr in (16, 600):
+        y, ref, g, og = run_pair(nl, x, PAPER, storage="f32", star_threshold=thr,
+                                 label=f"tiers T={thr}")
+        assert_close(y, ref, "f32", f"tiers T={thr}")
+
+
+def test_degenerate_netlists():
+    rng = np.random.default_rng(12)
+    x = rng.normal(0, 3, size=(6, 2))
+    cases = {
+        "no nets": handmade([], 6),
+        "only 0/1-pin and repeated-pin nets": handmade([[], [3], [2, 2, 2]], 6),
+        "one 2-pin net": handmade([[4, 1]], 6),
+        "parallel nets": handmade([[0, 1], [1, 0], [0, 1, 2], [5, 4, 4]], 6),
+    }
+    for name, nl in cases.items():
+        for terms in (PAPER, ([0.5], [3], [1.0])):
+            y, ref, g, og = run_pair(nl, x, terms, storage="f64", label=name)
+            assert_close(y, ref, "f64", name)
+
+
+def test_sigma_zero_isolated_rows():
+    nl = handmade([[0, 1], [1, 2, 3]], 6)  # cells 4, 5 isolated
+    x = np.arange(12, dtype=np.float64).reshape(6, 2) + 1
+    y, ref, g, og = run_pair(nl, x, ([0.0, 2.0], [2, 1], [0.5, 0.5]), storage="f64",
+                             label="sigma 0")
+    assert_close(y, ref, "f64", "sigma 0")
+    # (sigma s) s with s = 1/sqrt(sigma) is 1 only up to rounding
+    assert np.allclose(y[4:], 0.5 * x[4:], rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("cols", [1, 3, 8, 16, 19])
+def test_column_counts_and_leading_dimension(cols):
+    import torch
+    import paper_2502_17632_amd as gift
+    nl = W.sized(30_000, seed=77)
+    rng = np.random.default_rng(cols)
+    x = rng.normal(500, 20, size=(nl.num_cells, cols)).astype(np.float32)
+    og = O.build_netlist(nl, star_threshold=16)
+    g = gift.build_graph(nl.num_cells, nl.net_ptr, nl.pin_cell, star_threshold=16,
+                         sigmas=[2.0, 4.0])
+    wide = torch.zeros((nl.num_cells, cols + 5), dtype=torch.float32, device="cuda")
+    wide[:, 2:2 + cols] = torch.tensor(x, device="cuda")
+    xv = wide[:, 2:2 + cols]  # leading dimension cols + 5
+    out = torch.full((nl.num_cells, cols + 3), float("nan"), dtype=torch.float64, device="cuda")
+    ov = out[:, 1:1 + cols]
+    gift.filter_placement(g, *PAPER, xv, out=ov)
+    torch.cuda.synchronize()
+    y = ov.cpu().numpy()
+    ref = og.filter(x.astype(np.float64), *PAPER)
+    assert_close(y, ref, "f32", f"{cols} columns")
+    assert torch.isnan(out[:, 0]).all() and torch.isnan(out[:, 1 + cols:]).all()
+
+
+def test_fixed_rows_restored():
+    nl = W.tiny(seed=2)
+    x = W.make_signal(nl, seed=2)
+    y, ref, g, og = run_pair(nl, x, PAPER, storage="f32", fixed=nl.fixed, label="fixed")
+    assert_close(y, ref, "f32", "fixed")
+    fx = nl.fixed.astype(bool)
+    assert np.array_equal(y[fx], x[fx].astype(np.float32).astype(np.float64))
+
+
+def test_device_resident_netlist_and_determinism():
+    import torch
+    import paper_2502_17632_amd as gift
+    nl = W.sized(50_000, seed=5)
+    npd = torch.tensor(nl.net_ptr, device="cuda")
+    pcd = torch.tensor(nl.pin_cell, device="cuda")
+    g1 = gift.build_graph(nl.num_cells, npd, pcd, star_threshold=16, sigmas=[4.0])
+    g2 = gift.build_graph(nl.num_cells, nl.net_ptr, nl.pin_cell, star_threshold=16,
+                          sigmas=[4.0])
+    og = O.build_netlist(nl, star_threshold=16)
+    check_structure(g1, og)
+    for a, b in zip(g1.export(), g2.export()):
+        assert np.array_equal(a, b)
+    x = torch.tensor(W.make_signal(nl), dtype=torch.float32, device="cuda")
+    y1 = gift.filter_placement(g1, *EQ4, x)
+    y2 = gift.filter_placement(g1, *EQ4, x)
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2)
+
+
+def test_invalid_netlists_are_rejected():
+    import torch
+    import paper_2502_17632_amd as gift
+    bad = [
+        (np.array([0, 2, 3]), np.array([0, 1, 9])),  # pin out of range
+        (np.array([0, 2, 3]), np.array([0, -1, 1])),  # negative pin
+        (np.array([0, 3, 2]), np.array([0, 1])),  # decreasing net_ptr
+        (np.array([1, 2, 3]), np.array([0, 1, 1])),  # does not start at 0
+    ]
+    for net_ptr, pins in bad:
+        for dev in (False, True):
+            a, b = net_ptr.astype(np.int64), pins.astype(np.int32)
+            if dev:
+                a, b = torch.tensor(a, device="cuda"), torch.tensor(b, device="cuda")
+            with pytest.raises(gift.GiftError) as ei:
+                gift.build_graph(3, a, b)
+            assert ei.value.status == 1
+    with pytest.raises(ValueError):  # pin array shorter than net_ptr[-1]
+        gift.build_graph(3, np.array([0, 2, 5]), np.array([0, 1, 1]))
+    g = gift.build_graph(3, np.array([0, 2]), np.array([0, 1]), sigmas=[4.0])
+    x = torch.zeros((3, 2), device="cuda")
+    with pytest.raises(gift.GiftError):
+        gift.filter_placement(g, [2.0], [1], [1.0], x)  # sigma not prepared
+    with pytest.raises(gift.GiftError):
+        gift.filter_placement(g, [4.0], [0], [1.0], x)  # order 0
+    g.add_sigma(2.0)
+    gift.filter_placement(g, [2.0], [1], [1.0], x)
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_large_full_size(storage):
+    """The large workload (2M + 20k cells, 2.1M nets), as the benchmark runs it."""
+    nl = W.large()
+    x = W.make_signal(nl)
+    og = getattr(test_large_full_size, "_og", None)
+    if og is None:
+        log("[parity] building the large oracle graph")
+        og = O.build_netlist(nl, star_threshold=16)
+        test_large_full_size._og = og
+    y, ref, g, og = run_pair(nl, x, EQ5, storage=storage, star_threshold=16, og=og,
+                             label=f"large {storage}")
+    check_normalised(g, og, 4.0, storage)
+    assert_close(y, ref, storage, f"large {storage}")
