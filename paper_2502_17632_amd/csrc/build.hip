@@ -10,19 +10,24 @@
 // (eq. A_formulation) are rounded once to the storage type.
 //
 // Pipeline (all device work on the caller's stream):
-//   1. per net: distinct cells, ascending (tiers by pin count: 16-lane group,
-//      wave, block + LDS bitonic sort, block merge sort through global memory)
+//   0. check net_ptr; tile the nets (consecutive nets, at most a few thousand
+//      pins per tile, long nets alone)
+//   1. per net tile, in LDS: distinct cells of every net, ascending (rank of
+//      each pin among the net's first occurrences); long nets by a block-wide
+//      bitonic sort in LDS or a merge sort through global memory
 //   2. per net: clique or star, virtual id, weight
-//   3. per cell row: number of directed entries, exclusive scan -> offsets
-//   4. emit (col, net) keys into each row's slice (atomic slot reservation
-//      per pin, so the order inside a slice is arbitrary)
-//   5. per row: sort keys by (col, net) (same four tiers) and count distinct
-//      columns; the sorted order fixes the summation order, so the result
-//      does not depend on the emission order
-//   6. scan of distinct counts -> row_ptr; merge runs of equal col summing
-//      weights in ascending net id (float64); degree summed in ascending col
-//   7. star rows: the net's sorted cells with weight M w(M)
-//   8. per sigma: s_i = 1/sqrt(d_i + sigma), a_ij = (w_ij s_i) s_j,
+//   3. per cell row: number of directed entries (atomic histogram over pins),
+//      exclusive scan -> row slices; emit (col, net) keys into each row's
+//      slice (atomic slot reservation per pin: arbitrary order in a slice)
+//   4. per row tile, in LDS: sort each row's keys by (col, net) (rank among
+//      the row's keys, which are distinct), count distinct columns.  The
+//      sorted order fixes every summation order below, so the result does
+//      not depend on the emission order
+//   5. scan of distinct counts -> row_ptr; SpMM row tiles
+//   6. per row tile, in LDS: merge runs of equal col (weights summed in
+//      ascending net id, float64), write col / w, degree summed in ascending
+//      col; star rows copy the net's sorted cells with weight M w(M)
+//   7. per sigma: s_i = 1/sqrt(d_i + sigma), a_ij = (w_ij s_i) s_j,
 //      diag_i = (sigma s_i) s_i
 #include <cmath>
 #include <cstring>
@@ -36,16 +41,11 @@ namespace {
 
 enum : uint32_t { kFlagBadNetPtr = 1u, kFlagBadPin = 2u };
 
-constexpr int kBigCap32 = 8192;    // largest net sorted in LDS (32-bit keys)
-constexpr int kBigCap64 = 4096;    // largest row sorted in LDS (64-bit keys)
+constexpr int kNetSortCap = 8192;  // longest net sorted in LDS (32-bit keys)
+constexpr int kRowSortCap = 4096;  // longest row sorted in LDS (64-bit keys, 32 KB)
 constexpr int kChunk32 = 8192;     // LDS chunk of the global merge sort (u32)
 constexpr int kChunk64 = 4096;     // LDS chunk of the global merge sort (u64)
-
-__device__ __forceinline__ uint64_t group_mask(uint64_t ballot, int width) {
-  if (width == 64) return ballot;
-  int base = (threadIdx.x & 63) & ~(width - 1);
-  return (ballot >> base) & ((1ull << width) - 1ull);
-}
+constexpr int kSmemBytes = 46 * 1024;
 
 __device__ __forceinline__ double clique_weight(int64_t m, int model) {
   return model == GIFT_W_TWO_OVER_M ? 2.0 / static_cast<double>(m)
@@ -56,12 +56,26 @@ __device__ __forceinline__ double star_weight(int64_t m, int model) {
                                     : static_cast<double>(m) / static_cast<double>(m - 1);
 }
 
+__device__ __forceinline__ uint32_t key_col(uint64_t k) { return static_cast<uint32_t>(k >> 32); }
+__device__ __forceinline__ uint32_t key_net(uint64_t k) { return static_cast<uint32_t>(k); }
+
+// Fills seg[i] = k for every entry i of segment k (segments given by
+// local offsets loff[0..ns]); one thread per segment.
+__device__ __forceinline__ void fill_segment_ids(const int32_t *loff, int ns, uint16_t *seg) {
+  for (int k = threadIdx.x; k < ns; k += kBlock)
+    for (int i = loff[k]; i < loff[k + 1]; ++i) seg[i] = static_cast<uint16_t>(k);
+}
+
 // ---------------------------------------------------------------------------
-// 0. netlist checks that need no per-net work
+// 0. netlist checks
 // ---------------------------------------------------------------------------
-__global__ void k_check_ends(const int64_t *net_ptr, int64_t E, int64_t P, uint32_t *flag) {
-  if (threadIdx.x == 0 && blockIdx.x == 0)
-    if (net_ptr[0] != 0 || net_ptr[E] != P) atomicOr(flag, kFlagBadNetPtr);
+__global__ void k_check_netptr(const int64_t *net_ptr, int64_t E, int64_t P, uint32_t *flag) {
+  int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e > E) return;
+  const int64_t v = net_ptr[e];
+  bool bad = v < 0 || v > P || (e == 0 && v != 0) || (e == E && v != P) ||
+             (e < E && net_ptr[e + 1] < v);
+  if (bad) atomicOr(flag, kFlagBadNetPtr);
 }
 
 // ---------------------------------------------------------------------------
@@ -75,86 +89,44 @@ struct NetArgs {
   int32_t *ucell;    // sorted distinct cells at the net's pin offset
   int32_t *pin_net;  // net of every pin slot
   uint32_t *flag;
-  int32_t *list_out; // nets handed to the next tier
-  int32_t *count_out;
+  uint32_t *tmp32;   // scratch of the global merge sort [P]
+  const int32_t *tiles;
 };
 
-// Group of W lanes per net (nets with at most W pins); `list_in` NULL means
-// "net e = group index" (first tier), else the nets listed there.
-template <int W>
-__global__ __launch_bounds__(kBlock) void k_net_group(NetArgs a, const int32_t *list_in,
-                                                      const int32_t *count_in) {
-  const int t = threadIdx.x & (W - 1);
-  const int64_t groups = static_cast<int64_t>(gridDim.x) * (kBlock / W);
-  const int64_t n_items = list_in ? static_cast<int64_t>(*count_in) : a.E;
-  for (int64_t gi = static_cast<int64_t>(blockIdx.x) * (kBlock / W) + threadIdx.x / W;
-       gi < n_items; gi += groups) {
-    const int64_t e = list_in ? list_in[gi] : gi;
-    const int64_t lo = a.net_ptr[e], hi = a.net_ptr[e + 1];
-    if (lo < 0 || hi < lo || hi > a.P) {  // group-uniform
-      if (t == 0) {
-        atomicOr(a.flag, kFlagBadNetPtr);
-        a.M[e] = 0;
-      }
-      continue;
-    }
-    const int64_t m_raw = hi - lo;
-    if (m_raw > W) {
-      if (t == 0) a.list_out[atomicAdd(a.count_out, 1)] = static_cast<int32_t>(e);
-      continue;
-    }
-    const bool live = t < m_raw;
-    int32_t c = live ? a.pin[lo + t] : 0;
-    const bool bad = live && (c < 0 || c >= a.N);
-    const uint64_t badm = group_mask(__ballot(bad), W);
-    if (live) a.pin_net[lo + t] = static_cast<int32_t>(e);
-    if (badm) {
-      if (t == 0) {
-        atomicOr(a.flag, kFlagBadPin);
-        a.M[e] = 0;
-      }
-      continue;
-    }
-    // first occurrence of each cell, then its rank among distinct cells
-    bool first = live;
-    for (int s = 0; s < W; ++s) {
-      int32_t oc = __shfl(c, s, W);
-      if (s < t && s < m_raw && oc == c) first = false;
-    }
-    int less = 0;
-    for (int s = 0; s < W; ++s) {
-      int32_t oc = __shfl(c, s, W);
-      int of = __shfl(static_cast<int>(first), s, W);
-      if (s < m_raw && of && oc < c) ++less;
-    }
-    if (first) a.ucell[lo + less] = c;
-    const uint64_t fm = group_mask(__ballot(first), W);
-    if (t == 0) a.M[e] = __popcll(fm);
+// Writes the distinct values of the sorted keys src[0..n) to out[0..) and
+// returns their count.  Force-inlined at call sites whose `src` is known to be
+// LDS or global memory: a single pointer that may be either would make the
+// compiler address LDS through FLAT instructions.
+__device__ __forceinline__ int64_t write_distinct(const uint32_t *src, int64_t n, int32_t *out,
+                                                  int32_t *tmp) {
+  int64_t base = 0;
+  for (int64_t c0 = 0; c0 < n; c0 += kBlock) {
+    const int64_t i = c0 + threadIdx.x;
+    int f = 0;
+    if (i < n) f = (i == 0 || src[i] != src[i - 1]) ? 1 : 0;
+    int32_t total;
+    const int32_t pos = block_excl_scan<int32_t>(f, &total, tmp);
+    if (f) out[base + pos] = static_cast<int32_t>(src[i]);
+    base += total;
   }
+  return base;
 }
 
-// One block per net, pins sorted in LDS (nets with at most kBigCap pins).
-__global__ __launch_bounds__(kBlock) void k_net_block(NetArgs a, const int32_t *list_in,
-                                                      const int32_t *count_in) {
-  __shared__ uint32_t keys[kBigCap32];
-  __shared__ int32_t tmp[kBlock / kWave];
+// A net longer than kLongRow pins, alone in its tile.
+__device__ __forceinline__ void net_long(const NetArgs &a, int64_t e, int64_t lo, int64_t n,
+                                         unsigned char *smem) {
+  uint32_t *keys = reinterpret_cast<uint32_t *>(smem);
   __shared__ int bad_s;
-  const int64_t n_items = *count_in;
-  for (int64_t gi = blockIdx.x; gi < n_items; gi += gridDim.x) {
-    const int64_t e = list_in[gi];
-    const int64_t lo = a.net_ptr[e], hi = a.net_ptr[e + 1];
-    const int64_t m_raw = hi - lo;  // checked by the first tier
-    if (m_raw > kBigCap32) {
-      if (threadIdx.x == 0) a.list_out[atomicAdd(a.count_out, 1)] = static_cast<int32_t>(e);
-      continue;
-    }
-    if (threadIdx.x == 0) bad_s = 0;
-    __syncthreads();
-    const int np = next_pow2_i(static_cast<int>(m_raw));
+  __shared__ int32_t tmp[kBlock / kWave];
+  if (threadIdx.x == 0) bad_s = 0;
+  __syncthreads();
+  int64_t m;
+  if (n <= kNetSortCap) {
+    const int np = next_pow2_i(static_cast<int>(n));
     for (int i = threadIdx.x; i < np; i += kBlock) {
       uint32_t k = 0xffffffffu;
-      if (i < m_raw) {
-        int32_t c = a.pin[lo + i];
+      if (i < n) {
+        const int32_t c = a.pin[lo + i];
         a.pin_net[lo + i] = static_cast<int32_t>(e);
         if (c < 0 || c >= a.N) bad_s = 1;
         k = static_cast<uint32_t>(c);
@@ -162,76 +134,81 @@ __global__ __launch_bounds__(kBlock) void k_net_block(NetArgs a, const int32_t *
       keys[i] = k;
     }
     __syncthreads();
-    if (bad_s) {
-      if (threadIdx.x == 0) {
-        atomicOr(a.flag, kFlagBadPin);
-        a.M[e] = 0;
-      }
-      __syncthreads();
-      continue;
-    }
     lds_bitonic_sort<uint32_t>(keys, np);
-    int32_t base = 0;
-    for (int c0 = 0; c0 < m_raw; c0 += kBlock) {
-      int i = c0 + threadIdx.x;
-      int f = (i < m_raw && (i == 0 || keys[i] != keys[i - 1])) ? 1 : 0;
-      int32_t total;
-      int32_t pos = block_excl_scan<int32_t>(f, &total, tmp);
-      if (f) a.ucell[lo + base + pos] = static_cast<int32_t>(keys[i]);
-      base += total;
-    }
-    if (threadIdx.x == 0) a.M[e] = base;
-    __syncthreads();
-  }
-}
-
-// One block per net, merge sort through global memory (any size).
-__global__ __launch_bounds__(kBlock) void k_net_huge(NetArgs a, const int32_t *list_in,
-                                                     const int32_t *count_in, uint32_t *tmpbuf) {
-  __shared__ uint32_t lds[kChunk32];
-  __shared__ int32_t tmp[kBlock / kWave];
-  __shared__ int bad_s;
-  const int64_t n_items = *count_in;
-  for (int64_t gi = blockIdx.x; gi < n_items; gi += gridDim.x) {
-    const int64_t e = list_in[gi];
-    const int64_t lo = a.net_ptr[e], hi = a.net_ptr[e + 1];
-    const int64_t m_raw = hi - lo;
-    uint32_t *ka = reinterpret_cast<uint32_t *>(a.ucell) + lo;
-    uint32_t *kb = tmpbuf + lo;
-    if (threadIdx.x == 0) bad_s = 0;
-    __syncthreads();
-    for (int64_t i = threadIdx.x; i < m_raw; i += kBlock) {
-      int32_t c = a.pin[lo + i];
+    m = write_distinct(keys, n, a.ucell + lo, tmp);
+  } else {
+    uint32_t *ka = reinterpret_cast<uint32_t *>(a.ucell) + lo, *kb = a.tmp32 + lo;
+    for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+      const int32_t c = a.pin[lo + i];
       a.pin_net[lo + i] = static_cast<int32_t>(e);
       if (c < 0 || c >= a.N) bad_s = 1;
       ka[i] = static_cast<uint32_t>(c);
     }
     __syncthreads();
-    if (bad_s) {
-      if (threadIdx.x == 0) {
-        atomicOr(a.flag, kFlagBadPin);
-        a.M[e] = 0;
-      }
-      __syncthreads();
-      continue;
-    }
-    bool in_b = block_merge_sort_global<uint32_t, kChunk32>(ka, kb, m_raw, lds, 0xffffffffu);
-    if (!in_b) {
-      for (int64_t i = threadIdx.x; i < m_raw; i += kBlock) kb[i] = ka[i];
+    if (!block_merge_sort_global<uint32_t, kChunk32>(ka, kb, n, keys, 0xffffffffu)) {
+      for (int64_t i = threadIdx.x; i < n; i += kBlock) kb[i] = ka[i];
       __syncthreads();
     }
-    int64_t base = 0;
-    for (int64_t c0 = 0; c0 < m_raw; c0 += kBlock) {
-      int64_t i = c0 + threadIdx.x;
-      int f = (i < m_raw && (i == 0 || kb[i] != kb[i - 1])) ? 1 : 0;
-      int32_t total;
-      int32_t pos = block_excl_scan<int32_t>(f, &total, tmp);
-      if (f) ka[base + pos] = kb[i];
-      base += total;
-    }
-    if (threadIdx.x == 0) a.M[e] = static_cast<int32_t>(base);
-    __syncthreads();
+    m = write_distinct(kb, n, a.ucell + lo, tmp);
   }
+  if (threadIdx.x == 0) {
+    a.M[e] = static_cast<int32_t>(m);
+    if (bad_s) atomicOr(a.flag, kFlagBadPin);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_net_tiles(NetArgs a) {
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kSmemBytes];
+  __shared__ int bad_s;
+  const int64_t e0 = a.tiles[blockIdx.x], e1 = a.tiles[blockIdx.x + 1];
+  const int64_t q0 = a.net_ptr[e0], q1 = a.net_ptr[e1];
+  const int ns = static_cast<int>(e1 - e0);
+  const int64_t n64 = q1 - q0;
+  if (ns == 1 && n64 > kLongRow) {
+    net_long(a, e0, q0, n64, smem);
+    return;
+  }
+  const int n = static_cast<int>(n64);  // <= kTileCap
+  uint32_t *key = reinterpret_cast<uint32_t *>(smem);
+  int32_t *loff = reinterpret_cast<int32_t *>(key + kTileCap + 1);
+  uint16_t *seg = reinterpret_cast<uint16_t *>(loff + kTileRows + 2);
+  uint8_t *first = reinterpret_cast<uint8_t *>(seg + kTileCap + 1);
+  if (threadIdx.x == 0) bad_s = 0;
+  __syncthreads();
+  for (int k = threadIdx.x; k <= ns; k += kBlock) loff[k] = static_cast<int32_t>(a.net_ptr[e0 + k] - q0);
+  for (int i = threadIdx.x; i < n; i += kBlock) {
+    const int32_t c = a.pin[q0 + i];
+    if (c < 0 || c >= a.N) bad_s = 1;
+    key[i] = static_cast<uint32_t>(c);
+  }
+  __syncthreads();
+  fill_segment_ids(loff, ns, seg);
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += kBlock) {
+    const int k = seg[i];
+    a.pin_net[q0 + i] = static_cast<int32_t>(e0 + k);
+    uint8_t f = 1;
+    for (int j = loff[k]; j < i; ++j)
+      if (key[j] == key[i]) {
+        f = 0;
+        break;
+      }
+    first[i] = f;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += kBlock) {
+    if (!first[i]) continue;
+    const int k = seg[i];
+    int ur = 0;
+    for (int j = loff[k]; j < loff[k + 1]; ++j) ur += (first[j] && key[j] < key[i]) ? 1 : 0;
+    a.ucell[q0 + loff[k] + ur] = static_cast<int32_t>(key[i]);
+  }
+  for (int k = threadIdx.x; k < ns; k += kBlock) {
+    int m = 0;
+    for (int i = loff[k]; i < loff[k + 1]; ++i) m += first[i];
+    a.M[e0 + k] = m;
+  }
+  if (threadIdx.x == 0 && bad_s) atomicOr(a.flag, kFlagBadPin);
 }
 
 // ---------------------------------------------------------------------------
@@ -254,7 +231,7 @@ __global__ void k_virtual_map(const int32_t *is_star, const int64_t *vrank, int6
 }
 
 // ---------------------------------------------------------------------------
-// 3./4. count and emit the directed entries of cell rows
+// 3. count and emit the directed entries of cell rows
 // ---------------------------------------------------------------------------
 struct EmitArgs {
   const int64_t *net_ptr;
@@ -302,106 +279,84 @@ __global__ void k_emit(EmitArgs a, const int64_t *zoff, int32_t *cursor, uint64_
 }
 
 // ---------------------------------------------------------------------------
-// 5. sort each cell row's keys by (col, net); count distinct columns
+// 4. sort each cell row's keys by (col, net); count distinct columns
 // ---------------------------------------------------------------------------
 struct RowArgs {
   const int64_t *zoff;
-  uint64_t *zkey;   // emitted keys (also scratch of the huge tier)
+  uint64_t *zkey;   // emitted keys (also scratch of the global merge sort)
   uint64_t *zsort;  // sorted keys
   int32_t *ucnt;    // distinct columns per row
-  int64_t N;
-  int32_t *list_out;
-  int32_t *count_out;
+  const int32_t *tiles;
 };
 
-__device__ __forceinline__ uint32_t key_col(uint64_t k) { return static_cast<uint32_t>(k >> 32); }
-
-template <int W>
-__global__ __launch_bounds__(kBlock) void k_row_group(RowArgs a, const int32_t *list_in,
-                                                      const int32_t *count_in) {
-  const int t = threadIdx.x & (W - 1);
-  const int64_t groups = static_cast<int64_t>(gridDim.x) * (kBlock / W);
-  const int64_t n_items = list_in ? static_cast<int64_t>(*count_in) : a.N;
-  for (int64_t gi = static_cast<int64_t>(blockIdx.x) * (kBlock / W) + threadIdx.x / W;
-       gi < n_items; gi += groups) {
-    const int64_t r = list_in ? list_in[gi] : gi;
-    const int64_t lo = a.zoff[r], L = a.zoff[r + 1] - lo;
-    if (L > W) {
-      if (t == 0) a.list_out[atomicAdd(a.count_out, 1)] = static_cast<int32_t>(r);
-      continue;
-    }
-    if (L == 0) {
-      if (t == 0) a.ucnt[r] = 0;
-      continue;
-    }
-    const bool live = t < L;
-    const uint64_t k = live ? a.zkey[lo + t] : ~0ull;
-    int rank = 0;
-    for (int s = 0; s < W; ++s) {
-      uint64_t o = __shfl(k, s, W);
-      if (s < L && o < k) ++rank;
-    }
-    // column of the key ranked just below this one
-    uint64_t prev = ~0ull;
-    for (int s = 0; s < W; ++s) {
-      int orank = __shfl(rank, s, W);
-      uint64_t o = __shfl(k, s, W);
-      if (s < L && orank == rank - 1) prev = o;
-    }
-    if (live) a.zsort[lo + rank] = k;
-    const bool head = live && (rank == 0 || key_col(prev) != key_col(k));
-    const uint64_t hm = group_mask(__ballot(head), W);
-    if (t == 0) a.ucnt[r] = __popcll(hm);
-  }
+__device__ int32_t count_heads_block(const uint64_t *k, int64_t n, int32_t *tmp) {
+  int32_t heads = 0;
+  for (int64_t i = threadIdx.x; i < n; i += kBlock)
+    if (i == 0 || key_col(k[i]) != key_col(k[i - 1])) ++heads;
+  return block_sum<int32_t>(heads, tmp);
 }
 
-__global__ __launch_bounds__(kBlock) void k_row_block(RowArgs a, const int32_t *list_in,
-                                                      const int32_t *count_in) {
-  __shared__ uint64_t keys[kBigCap64];
+__global__ __launch_bounds__(kBlock) void k_row_sort_tiles(RowArgs a) {
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kSmemBytes];
   __shared__ int32_t tmp[kBlock / kWave];
-  const int64_t n_items = *count_in;
-  for (int64_t gi = blockIdx.x; gi < n_items; gi += gridDim.x) {
-    const int64_t r = list_in[gi];
-    const int64_t lo = a.zoff[r], L = a.zoff[r + 1] - lo;
-    if (L > kBigCap64) {
-      if (threadIdx.x == 0) a.list_out[atomicAdd(a.count_out, 1)] = static_cast<int32_t>(r);
-      continue;
-    }
-    const int np = next_pow2_i(static_cast<int>(L));
-    for (int i = threadIdx.x; i < np; i += kBlock) keys[i] = i < L ? a.zkey[lo + i] : ~0ull;
-    __syncthreads();
-    lds_bitonic_sort<uint64_t>(keys, np);
-    int32_t heads = 0;
-    for (int i = threadIdx.x; i < L; i += kBlock) {
-      a.zsort[lo + i] = keys[i];
-      if (i == 0 || key_col(keys[i]) != key_col(keys[i - 1])) ++heads;
-    }
-    int32_t total = block_sum<int32_t>(heads, tmp);
-    if (threadIdx.x == 0) a.ucnt[r] = total;
-    __syncthreads();
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void k_row_huge(RowArgs a, const int32_t *list_in,
-                                                     const int32_t *count_in) {
-  __shared__ uint64_t lds[kChunk64];
-  __shared__ int32_t tmp[kBlock / kWave];
-  const int64_t n_items = *count_in;
-  for (int64_t gi = blockIdx.x; gi < n_items; gi += gridDim.x) {
-    const int64_t r = list_in[gi];
-    const int64_t lo = a.zoff[r], L = a.zoff[r + 1] - lo;
-    uint64_t *ka = a.zkey + lo, *kb = a.zsort + lo;
-    bool in_b = block_merge_sort_global<uint64_t, kChunk64>(ka, kb, L, lds, ~0ull);
-    if (!in_b) {
-      for (int64_t i = threadIdx.x; i < L; i += kBlock) kb[i] = ka[i];
+  const int64_t r0 = a.tiles[blockIdx.x], r1 = a.tiles[blockIdx.x + 1];
+  const int64_t z0 = a.zoff[r0], z1 = a.zoff[r1];
+  const int ns = static_cast<int>(r1 - r0);
+  const int64_t n64 = z1 - z0;
+  if (ns == 1 && n64 > kLongRow) {
+    uint64_t *keys = reinterpret_cast<uint64_t *>(smem);
+    int32_t total;
+    if (n64 <= kRowSortCap) {
+      const int np = next_pow2_i(static_cast<int>(n64));
+      for (int i = threadIdx.x; i < np; i += kBlock) keys[i] = i < n64 ? a.zkey[z0 + i] : ~0ull;
       __syncthreads();
+      lds_bitonic_sort<uint64_t>(keys, np);
+      for (int i = threadIdx.x; i < n64; i += kBlock) a.zsort[z0 + i] = keys[i];
+      total = count_heads_block(keys, n64, tmp);
+    } else {
+      uint64_t *ka = a.zkey + z0, *kb = a.zsort + z0;
+      if (!block_merge_sort_global<uint64_t, kChunk64>(ka, kb, n64, keys, ~0ull)) {
+        for (int64_t i = threadIdx.x; i < n64; i += kBlock) kb[i] = ka[i];
+        __syncthreads();
+      }
+      total = count_heads_block(kb, n64, tmp);
     }
-    int32_t heads = 0;
-    for (int64_t i = threadIdx.x; i < L; i += kBlock)
-      if (i == 0 || key_col(kb[i]) != key_col(kb[i - 1])) ++heads;
-    int32_t total = block_sum<int32_t>(heads, tmp);
-    if (threadIdx.x == 0) a.ucnt[r] = total;
-    __syncthreads();
+    if (threadIdx.x == 0) a.ucnt[r0] = total;
+    return;
+  }
+  const int n = static_cast<int>(n64);
+  uint64_t *key = reinterpret_cast<uint64_t *>(smem);
+  int32_t *loff = reinterpret_cast<int32_t *>(key + kTileCap + 1);
+  uint16_t *seg = reinterpret_cast<uint16_t *>(loff + kTileRows + 2);
+  uint8_t *head = reinterpret_cast<uint8_t *>(seg + kTileCap + 1);
+  for (int k = threadIdx.x; k <= ns; k += kBlock) loff[k] = static_cast<int32_t>(a.zoff[r0 + k] - z0);
+  for (int i = threadIdx.x; i < n; i += kBlock) key[i] = a.zkey[z0 + i];
+  __syncthreads();
+  fill_segment_ids(loff, ns, seg);
+  __syncthreads();
+  // rank of each key in its row (keys of a row are distinct); the key is the
+  // first of its column when no smaller key of the row has the same column
+  for (int i = threadIdx.x; i < n; i += kBlock) {
+    const int k = seg[i];
+    const uint64_t me = key[i];
+    const uint32_t mc = key_col(me);
+    int rank = 0;
+    uint8_t h = 1;
+    for (int j = loff[k]; j < loff[k + 1]; ++j) {
+      const uint64_t o = key[j];
+      if (o < me) {
+        ++rank;
+        if (key_col(o) == mc) h = 0;
+      }
+    }
+    a.zsort[z0 + loff[k] + rank] = me;
+    head[i] = h;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < ns; k += kBlock) {
+    int h = 0;
+    for (int i = loff[k]; i < loff[k + 1]; ++i) h += head[i];
+    a.ucnt[r0 + k] = h;
   }
 }
 
@@ -417,42 +372,110 @@ __global__ void k_row_ptr32(const int64_t *rp64, int64_t n, int32_t *rp32) {
 }
 
 // ---------------------------------------------------------------------------
-// 6./7. merge into the CSR of A, degrees
+// 6. merge into the CSR of A, degrees
 // ---------------------------------------------------------------------------
-__global__ void k_merge_cells(const int64_t *zoff, const uint64_t *zsort, const double *wnet,
-                              const int32_t *row_ptr, int64_t N, int32_t *col, double *w,
-                              double *deg) {
-  int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (r >= N) return;
-  const int64_t lo = zoff[r], hi = zoff[r + 1];
-  int64_t out = row_ptr[r];
-  double d = 0.0;
-  uint32_t cur = 0;
-  double acc = 0.0;
-  for (int64_t p = lo; p < hi; ++p) {
-    uint64_t k = zsort[p];
-    uint32_t c = key_col(k);
-    double wk = wnet[static_cast<uint32_t>(k)];
-    if (p == lo) {
-      cur = c;
-      acc = wk;
-    } else if (c == cur) {
-      acc = acc + wk;
-    } else {
-      col[out] = static_cast<int32_t>(cur);
-      w[out] = acc;
-      ++out;
-      d = d + acc;
-      cur = c;
-      acc = wk;
+struct MergeArgs {
+  const int64_t *zoff;
+  const uint64_t *zsort;
+  const double *wnet;
+  const int32_t *row_ptr;
+  const int32_t *tiles;
+  int32_t *col;
+  double *w;
+  double *deg;
+};
+
+// Weight of the run of equal columns starting at sorted entry i (ascending
+// net id), reading the keys from `k` (length n).
+__device__ __forceinline__ double run_weight(const uint64_t *k, int64_t i, int64_t n,
+                                             const double *wnet) {
+  const uint32_t c = key_col(k[i]);
+  double s = wnet[key_net(k[i])];
+  for (int64_t j = i + 1; j < n && key_col(k[j]) == c; ++j) s = s + wnet[key_net(k[j])];
+  return s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_row_merge_tiles(MergeArgs a) {
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kSmemBytes];
+  __shared__ int32_t tmp[kBlock / kWave];
+  const int64_t r0 = a.tiles[blockIdx.x], r1 = a.tiles[blockIdx.x + 1];
+  const int64_t z0 = a.zoff[r0], z1 = a.zoff[r1];
+  const int ns = static_cast<int>(r1 - r0);
+  const int64_t n64 = z1 - z0;
+  const int64_t o0 = a.row_ptr[r0];
+  if (ns == 1 && n64 > kLongRow) {
+    // one long row: chunks of kBlock keys straight from global memory
+    const uint64_t *k = a.zsort + z0;
+    double *mw = reinterpret_cast<double *>(smem);
+    int64_t base = 0;
+    for (int64_t c0 = 0; c0 < n64; c0 += kBlock) {
+      const int64_t i = c0 + threadIdx.x;
+      const int f = (i < n64 && (i == 0 || key_col(k[i]) != key_col(k[i - 1]))) ? 1 : 0;
+      int32_t total;
+      const int32_t pos = block_excl_scan<int32_t>(f, &total, tmp);
+      if (f) {
+        a.col[o0 + base + pos] = static_cast<int32_t>(key_col(k[i]));
+        a.w[o0 + base + pos] = run_weight(k, i, n64, a.wnet);
+      }
+      base += total;
+    }
+    __syncthreads();
+    // degree: ascending column, staged through LDS in chunks
+    double d = 0.0;
+    constexpr int kChunk = kSmemBytes / 8;
+    for (int64_t c0 = 0; c0 < base; c0 += kChunk) {
+      const int len = static_cast<int>(base - c0 < kChunk ? base - c0 : kChunk);
+      for (int i = threadIdx.x; i < len; i += kBlock) mw[i] = a.w[o0 + c0 + i];
+      __syncthreads();
+      if (threadIdx.x == 0)
+        for (int i = 0; i < len; ++i) d = d + mw[i];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) a.deg[r0] = d;
+    return;
+  }
+  const int n = static_cast<int>(n64);
+  uint64_t *key = reinterpret_cast<uint64_t *>(smem);
+  double *mw = reinterpret_cast<double *>(key + kTileCap + 1);
+  int32_t *loff = reinterpret_cast<int32_t *>(mw + kTileCap + 1);
+  int32_t *moff = loff + kTileRows + 2;
+  uint16_t *seg = reinterpret_cast<uint16_t *>(moff + kTileRows + 2);
+  for (int k = threadIdx.x; k <= ns; k += kBlock) {
+    loff[k] = static_cast<int32_t>(a.zoff[r0 + k] - z0);
+    moff[k] = static_cast<int32_t>(a.row_ptr[r0 + k] - o0);
+  }
+  for (int i = threadIdx.x; i < n; i += kBlock) key[i] = a.zsort[z0 + i];
+  __syncthreads();
+  fill_segment_ids(loff, ns, seg);
+  __syncthreads();
+  // each thread owns a contiguous chunk of entries; heads are numbered by a
+  // block scan, which also numbers the merged entries of the tile in order
+  constexpr int kPer = (kTileCap + kBlock - 1) / kBlock;
+  const int b = threadIdx.x * kPer;
+  int mine = 0;
+  for (int i = b; i < b + kPer && i < n; ++i)
+    mine += (i == loff[seg[i]] || key_col(key[i]) != key_col(key[i - 1])) ? 1 : 0;
+  int32_t total;
+  int32_t pos = block_excl_scan<int32_t>(mine, &total, tmp);
+  for (int i = b; i < b + kPer && i < n; ++i) {
+    const int k = seg[i];
+    const int end = loff[k + 1];
+    if (i == loff[k] || key_col(key[i]) != key_col(key[i - 1])) {
+      const uint32_t c = key_col(key[i]);
+      double s = a.wnet[key_net(key[i])];
+      for (int j = i + 1; j < end && key_col(key[j]) == c; ++j) s = s + a.wnet[key_net(key[j])];
+      a.col[o0 + pos] = static_cast<int32_t>(c);
+      a.w[o0 + pos] = s;
+      mw[pos] = s;
+      ++pos;
     }
   }
-  if (hi > lo) {
-    col[out] = static_cast<int32_t>(cur);
-    w[out] = acc;
-    d = d + acc;
+  __syncthreads();
+  for (int k = threadIdx.x; k < ns; k += kBlock) {
+    double d = 0.0;
+    for (int i = moff[k]; i < moff[k + 1]; ++i) d = d + mw[i];
+    a.deg[r0 + k] = d;
   }
-  deg[r] = d;
 }
 
 // One wave per star row: the net's sorted cells, weight M w(M).
@@ -484,7 +507,7 @@ __global__ __launch_bounds__(kBlock) void k_star_rows(const int32_t *virt_net,
 }
 
 // ---------------------------------------------------------------------------
-// 8. normalisation for one sigma
+// 7. normalisation for one sigma
 // ---------------------------------------------------------------------------
 template <int D>
 __global__ void k_sigma_scale(const double *deg, int64_t R, double sigma, double *s,
@@ -497,18 +520,35 @@ __global__ void k_sigma_scale(const double *deg, int64_t R, double sigma, double
   diag[i] = static_cast<typename Store<D>::A>((sigma * si) * si);
 }
 
+// One block per SpMM row tile: a_ij = (w_ij s_i) s_j for the tile's entries.
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_sigma_values(const int32_t *row_ptr,
+                                                         const int32_t *tiles,
                                                          const int32_t *col, const double *w,
-                                                         const double *s, int64_t R,
+                                                         const double *s,
                                                          typename Store<D>::T *val) {
-  constexpr int G = 8;
-  const int t = threadIdx.x & (G - 1);
-  const int64_t r = (static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x) / G;
-  if (r >= R) return;
-  const double si = s[r];
-  for (int64_t p = row_ptr[r] + t; p < row_ptr[r + 1]; p += G)
-    val[p] = Store<D>::from_f64((w[p] * si) * s[col[p]]);
+  __shared__ int32_t loff[kTileRows + 2];
+  __shared__ uint16_t seg[kTileCap + 1];
+  __shared__ double ls[kTileRows + 1];
+  const int64_t r0 = tiles[blockIdx.x], r1 = tiles[blockIdx.x + 1];
+  const int64_t p0 = row_ptr[r0], p1 = row_ptr[r1];
+  const int ns = static_cast<int>(r1 - r0);
+  if (ns == 1 && p1 - p0 > kLongRow) {
+    const double si = s[r0];
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += kBlock)
+      val[p] = Store<D>::from_f64((w[p] * si) * s[col[p]]);
+    return;
+  }
+  const int n = static_cast<int>(p1 - p0);
+  for (int k = threadIdx.x; k <= ns; k += kBlock) loff[k] = static_cast<int32_t>(row_ptr[r0 + k] - p0);
+  for (int k = threadIdx.x; k < ns; k += kBlock) ls[k] = s[r0 + k];
+  __syncthreads();
+  fill_segment_ids(loff, ns, seg);
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += kBlock) {
+    const int64_t p = p0 + i;
+    val[p] = Store<D>::from_f64((w[p] * ls[seg[i]]) * s[col[p]]);
+  }
 }
 
 template <int D>
@@ -521,9 +561,12 @@ gift_status sigma_kernels(gift_graph *g, double sigma, SigmaBlock &b, hipStream_
   k_sigma_scale<D><<<grid_for(g->num_rows), kBlock, 0, st>>>(g->deg, g->num_rows, sigma, s,
                                                                static_cast<A *>(b.diag));
   GIFT_TRY(check_launch("k_sigma_scale"));
-  k_sigma_values<D><<<grid_for(g->num_rows * 8), kBlock, 0, st>>>(
-      g->row_ptr, g->col, g->w, s, g->num_rows, static_cast<T *>(b.val));
-  return check_launch("k_sigma_values");
+  if (g->num_tiles > 0) {
+    k_sigma_values<D><<<static_cast<unsigned>(g->num_tiles), kBlock, 0, st>>>(
+        g->row_ptr, g->tile_row, g->col, g->w, s, static_cast<T *>(b.val));
+    GIFT_TRY(check_launch("k_sigma_values"));
+  }
+  return GIFT_OK;
 }
 
 }  // namespace
@@ -559,7 +602,32 @@ gift_status prepare_sigma(gift_graph *g, double sigma, hipStream_t st) {
 
 namespace {
 
-unsigned list_grid() { return 2048; }
+constexpr int kMaxReadback = 8;
+
+// Copies int64 scalars from device memory into one small block so the host
+// reads them with a single transfer.
+struct ReadbackPtrs {
+  const int64_t *p[kMaxReadback];
+};
+__global__ void k_gather_i64(ReadbackPtrs src, int n, int64_t *dst) {
+  if (threadIdx.x < n) dst[threadIdx.x] = *src.p[threadIdx.x];
+}
+
+// Reads `n` device int64 scalars with one launch, one copy and one sync.
+gift_status read_scalars(Scratch &sc, hipStream_t st, const int64_t *const *ptrs, int n,
+                         int64_t *out) {
+  int64_t *dev = nullptr;
+  GIFT_TRY(sc.get(&dev, kMaxReadback, "readback"));
+  ReadbackPtrs rp{};
+  for (int i = 0; i < n; ++i) rp.p[i] = ptrs[i];
+  k_gather_i64<<<1, 64, 0, st>>>(rp, n, dev);
+  GIFT_TRY(check_launch("k_gather_i64"));
+  GIFT_HIP(hipMemcpyAsync(out, dev, n * 8, hipMemcpyDeviceToHost, st));
+  GIFT_HIP(hipStreamSynchronize(st));
+  return GIFT_OK;
+}
+
+__global__ void k_flag_to_i64(const uint32_t *flag, int64_t *out) { *out = *flag; }
 
 gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) {
   const int64_t N = d->num_cells, E = d->num_nets;
@@ -589,40 +657,47 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
                      (long long)P, (long long)(N + E));
 
   uint32_t *flag = nullptr;
-  int32_t *M = nullptr, *ucell = nullptr, *pin_net = nullptr, *lists = nullptr, *counts = nullptr;
-  uint32_t *tmp32 = nullptr;
+  int64_t *flag64 = nullptr;
   GIFT_TRY(sc.get(&flag, 1, "flag"));
+  GIFT_TRY(sc.get(&flag64, 1, "flag copy"));
+  GIFT_HIP(hipMemsetAsync(flag, 0, 4, st));
+
+  // 0. check net_ptr (read back before anything trusts it), tile the nets
+  k_check_netptr<<<grid_for(E + 1), kBlock, 0, st>>>(net_ptr, E, P, flag);
+  GIFT_TRY(check_launch("k_check_netptr"));
+  k_flag_to_i64<<<1, 1, 0, st>>>(flag, flag64);
+  GIFT_TRY(check_launch("k_flag_to_i64"));
+  int64_t h0 = 0;
+  {
+    const int64_t *ptrs[1] = {flag64};
+    GIFT_TRY(read_scalars(sc, st, ptrs, 1, &h0));
+  }
+  if (h0 & kFlagBadNetPtr)
+    return set_error(GIFT_EINVAL, "net_ptr must start at 0, end at the pin count and not decrease");
+  int32_t *net_tiles = nullptr;
+  int64_t *net_tile_counts = nullptr;
+  GIFT_TRY(sc.get(&net_tiles, E + 2, "net tiles"));
+  GIFT_TRY(sc.get(&net_tile_counts, 2, "net tile counts"));
+  GIFT_TRY(build_tiles64(net_ptr, E, E, st, net_tiles, net_tile_counts));
+  int64_t num_net_tiles = 0;
+  {
+    const int64_t *ptrs[1] = {net_tile_counts};
+    GIFT_TRY(read_scalars(sc, st, ptrs, 1, &num_net_tiles));
+  }
+
+  int32_t *M = nullptr, *ucell = nullptr, *pin_net = nullptr;
+  uint32_t *tmp32 = nullptr;
   GIFT_TRY(sc.get(&M, E, "net sizes"));
   GIFT_TRY(sc.get(&ucell, P, "distinct cells"));
   GIFT_TRY(sc.get(&pin_net, P, "pin nets"));
   GIFT_TRY(sc.get(&tmp32, P, "net sort scratch"));
-  const int64_t list_cap = (E > N ? E : N) + 1;
-  GIFT_TRY(sc.get(&lists, 3 * list_cap, "tier lists"));
-  GIFT_TRY(sc.get(&counts, 8, "tier counts"));
-  GIFT_HIP(hipMemsetAsync(flag, 0, 4, st));
-  GIFT_HIP(hipMemsetAsync(counts, 0, 8 * 4, st));
-  GIFT_HIP(hipMemsetAsync(pin_net, 0xff, P * 4 + 4, st));
 
-  k_check_ends<<<1, 64, 0, st>>>(net_ptr, E, P, flag);
-  GIFT_TRY(check_launch("k_check_ends"));
-
-  // 1. distinct cells per net, four tiers
-  NetArgs na{net_ptr, pin, E, P, N, M, ucell, pin_net, flag, nullptr, nullptr};
-  int32_t *l1 = lists, *l2 = lists + list_cap, *l3 = lists + 2 * list_cap;
-  na.list_out = l1;
-  na.count_out = counts + 0;
-  k_net_group<16><<<grid_for(E * 16), kBlock, 0, st>>>(na, nullptr, nullptr);
-  GIFT_TRY(check_launch("k_net_group<16>"));
-  na.list_out = l2;
-  na.count_out = counts + 1;
-  k_net_group<64><<<list_grid(), kBlock, 0, st>>>(na, l1, counts + 0);
-  GIFT_TRY(check_launch("k_net_group<64>"));
-  na.list_out = l3;
-  na.count_out = counts + 2;
-  k_net_block<<<list_grid(), kBlock, 0, st>>>(na, l2, counts + 1);
-  GIFT_TRY(check_launch("k_net_block"));
-  k_net_huge<<<256, kBlock, 0, st>>>(na, l3, counts + 2, tmp32);
-  GIFT_TRY(check_launch("k_net_huge"));
+  // 1. distinct cells per net
+  if (num_net_tiles > 0) {
+    NetArgs na{net_ptr, pin, E, P, N, M, ucell, pin_net, flag, tmp32, net_tiles};
+    k_net_tiles<<<static_cast<unsigned>(num_net_tiles), kBlock, 0, st>>>(na);
+    GIFT_TRY(check_launch("k_net_tiles"));
+  }
 
   // 2. classify
   int32_t *is_star = nullptr, *virt_net = nullptr;
@@ -639,38 +714,37 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
   k_virtual_map<<<grid_for(E), kBlock, 0, st>>>(is_star, vrank, E, virt_net);
   GIFT_TRY(check_launch("k_virtual_map"));
 
-  // 3. entries per cell row
-  int32_t *cnt = nullptr;
-  int64_t *zoff = nullptr;
+  // 3. entries per cell row, row tiles over the pre-merge slices
+  int32_t *cnt = nullptr, *row_tiles = nullptr;
+  int64_t *zoff = nullptr, *row_tile_counts = nullptr;
   GIFT_TRY(sc.get(&cnt, N, "row counts"));
   GIFT_TRY(sc.get(&zoff, N + 1, "row offsets"));
+  GIFT_TRY(sc.get(&row_tiles, N + 2, "row tiles"));
+  GIFT_TRY(sc.get(&row_tile_counts, 2, "row tile counts"));
   GIFT_HIP(hipMemsetAsync(cnt, 0, N * 4 + 4, st));
   EmitArgs ea{net_ptr, ucell, pin_net, M, is_star, vrank, E, P, N};
   k_count<<<grid_for(P), kBlock, 0, st>>>(ea, cnt);
   GIFT_TRY(check_launch("k_count"));
   GIFT_TRY(scan_i32_to_i64(cnt, zoff, N, st));
+  GIFT_TRY(build_tiles64(zoff, N, N, st, row_tiles, row_tile_counts));
+  k_flag_to_i64<<<1, 1, 0, st>>>(flag, flag64);
+  GIFT_TRY(check_launch("k_flag_to_i64"));
 
-  // sizes back to the host
-  struct Sizes {
-    uint32_t flag;
-    uint32_t pad;
-    int64_t V, Z;
-  } hs{};
-  GIFT_HIP(hipMemcpyAsync(&hs.flag, flag, 4, hipMemcpyDeviceToHost, st));
-  GIFT_HIP(hipMemcpyAsync(&hs.V, vrank + E, 8, hipMemcpyDeviceToHost, st));
-  GIFT_HIP(hipMemcpyAsync(&hs.Z, zoff + N, 8, hipMemcpyDeviceToHost, st));
-  GIFT_HIP(hipStreamSynchronize(st));
-  if (hs.flag & kFlagBadNetPtr)
-    return set_error(GIFT_EINVAL, "net_ptr must start at 0, end at the pin count and not decrease");
-  if (hs.flag & kFlagBadPin) return set_error(GIFT_EINVAL, "a pin names a cell outside [0, num_cells)");
-  const int64_t V = hs.V, Z = hs.Z, R = N + V;
+  // sizes back to the host: flag, V, Z, row tiles
+  int64_t h1[4] = {0, 0, 0, 0};
+  {
+    const int64_t *ptrs[4] = {flag64, vrank + E, zoff + N, row_tile_counts};
+    GIFT_TRY(read_scalars(sc, st, ptrs, 4, h1));
+  }
+  if (h1[0] & kFlagBadPin) return set_error(GIFT_EINVAL, "a pin names a cell outside [0, num_cells)");
+  const int64_t V = h1[1], Z = h1[2], num_row_tiles = h1[3], R = N + V;
   if (R >= (int64_t(1) << 31))
     return set_error(GIFT_EUNSUPPORTED, "too many rows (%lld)", (long long)R);
   g->num_cells = N;
   g->num_virtual = V;
   g->num_rows = R;
 
-  // 4. emit
+  // 3b. emit
   uint64_t *zkey = nullptr, *zsort = nullptr;
   int32_t *cursor = nullptr, *ucnt = nullptr;
   GIFT_TRY(sc.get(&zkey, Z, "emitted keys"));
@@ -681,60 +755,59 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
   k_emit<<<grid_for(P), kBlock, 0, st>>>(ea, zoff, cursor, zkey);
   GIFT_TRY(check_launch("k_emit"));
 
-  // 5. sort rows, four tiers
-  RowArgs ra{zoff, zkey, zsort, ucnt, N, nullptr, nullptr};
-  ra.list_out = l1;
-  ra.count_out = counts + 3;
-  k_row_group<16><<<grid_for(N * 16), kBlock, 0, st>>>(ra, nullptr, nullptr);
-  GIFT_TRY(check_launch("k_row_group<16>"));
-  ra.list_out = l2;
-  ra.count_out = counts + 4;
-  k_row_group<64><<<list_grid(), kBlock, 0, st>>>(ra, l1, counts + 3);
-  GIFT_TRY(check_launch("k_row_group<64>"));
-  ra.list_out = l3;
-  ra.count_out = counts + 5;
-  k_row_block<<<list_grid(), kBlock, 0, st>>>(ra, l2, counts + 4);
-  GIFT_TRY(check_launch("k_row_block"));
-  k_row_huge<<<256, kBlock, 0, st>>>(ra, l3, counts + 5);
-  GIFT_TRY(check_launch("k_row_huge"));
-  k_virtual_counts<<<grid_for(V), kBlock, 0, st>>>(virt_net, M, N, V, ucnt);
-  GIFT_TRY(check_launch("k_virtual_counts"));
+  // 4. sort rows
+  if (num_row_tiles > 0) {
+    RowArgs ra{zoff, zkey, zsort, ucnt, row_tiles};
+    k_row_sort_tiles<<<static_cast<unsigned>(num_row_tiles), kBlock, 0, st>>>(ra);
+    GIFT_TRY(check_launch("k_row_sort_tiles"));
+  }
+  if (V > 0) {
+    k_virtual_counts<<<grid_for(V), kBlock, 0, st>>>(virt_net, M, N, V, ucnt);
+    GIFT_TRY(check_launch("k_virtual_counts"));
+  }
 
-  // 6. row_ptr
+  // 5. row_ptr and the SpMM row tiles
   int64_t *rp64 = nullptr;
   GIFT_TRY(sc.get(&rp64, R + 1, "row offsets (64-bit)"));
   GIFT_TRY(scan_i32_to_i64(ucnt, rp64, R, st));
-  int64_t nnz = 0, nnz_cells = 0;
-  GIFT_HIP(hipMemcpyAsync(&nnz, rp64 + R, 8, hipMemcpyDeviceToHost, st));
-  GIFT_HIP(hipMemcpyAsync(&nnz_cells, rp64 + N, 8, hipMemcpyDeviceToHost, st));
-  GIFT_HIP(hipStreamSynchronize(st));
-  g->nnz_cells = nnz_cells;
+  int64_t *tile_counts = nullptr;
+  GIFT_TRY(dev_alloc(reinterpret_cast<void **>(&g->tile_row), (R + 2) * 4, st, "row tiles"));
+  GIFT_TRY(sc.get(&tile_counts, 2, "tile counts"));
+  GIFT_TRY(build_tiles64(rp64, R, N, st, g->tile_row, tile_counts));
+  int64_t h2[4] = {0, 0, 0, 0};
+  {
+    const int64_t *ptrs[4] = {rp64 + R, rp64 + N, tile_counts, tile_counts + 1};
+    GIFT_TRY(read_scalars(sc, st, ptrs, 4, h2));
+  }
+  const int64_t nnz = h2[0];
   if (nnz >= (int64_t(1) << 31))
     return set_error(GIFT_EUNSUPPORTED, "too many stored entries (%lld)", (long long)nnz);
   g->nnz = nnz;
+  g->nnz_cells = h2[1];
+  g->num_tiles = h2[2];
+  g->num_tiles_cells = h2[3];
   GIFT_TRY(dev_alloc(reinterpret_cast<void **>(&g->row_ptr), (R + 1) * 4, st, "row_ptr"));
   GIFT_TRY(dev_alloc(reinterpret_cast<void **>(&g->col), nnz * 4, st, "col"));
   GIFT_TRY(dev_alloc(reinterpret_cast<void **>(&g->w), nnz * 8, st, "weights"));
   GIFT_TRY(dev_alloc(reinterpret_cast<void **>(&g->deg), R * 8, st, "degrees"));
-  g->bytes = (R + 1) * 4 + nnz * 12 + R * 8;
+  g->bytes = (R + 1) * 4 + nnz * 12 + R * 8 + (R + 2) * 4;
   k_row_ptr32<<<grid_for(R + 1), kBlock, 0, st>>>(rp64, R, g->row_ptr);
   GIFT_TRY(check_launch("k_row_ptr32"));
 
-  // 7. merge
-  k_merge_cells<<<grid_for(N), kBlock, 0, st>>>(zoff, zsort, wnet, g->row_ptr, N, g->col, g->w,
-                                                g->deg);
-  GIFT_TRY(check_launch("k_merge_cells"));
-  k_star_rows<<<grid_for(V * kWave), kBlock, 0, st>>>(virt_net, net_ptr, M, ucell, wnet,
-                                                       g->row_ptr, N, V, g->col, g->w, g->deg);
-  GIFT_TRY(check_launch("k_star_rows"));
+  // 6. merge
+  if (num_row_tiles > 0) {
+    MergeArgs ma{zoff, zsort, wnet, g->row_ptr, row_tiles, g->col, g->w, g->deg};
+    k_row_merge_tiles<<<static_cast<unsigned>(num_row_tiles), kBlock, 0, st>>>(ma);
+    GIFT_TRY(check_launch("k_row_merge_tiles"));
+  }
+  if (V > 0) {
+    k_star_rows<<<grid_for(V * kWave), kBlock, 0, st>>>(virt_net, net_ptr, M, ucell, wnet,
+                                                         g->row_ptr, N, V, g->col, g->w, g->deg);
+    GIFT_TRY(check_launch("k_star_rows"));
+  }
 
-  // 8. normalisation
+  // 7. normalisation
   for (int32_t i = 0; i < d->num_sigmas; ++i) GIFT_TRY(prepare_sigma(g, d->sigmas[i], st));
-
-  // choose the SpMM row split from the mean row lengths
-  double mean_cells = N ? static_cast<double>(nnz) / static_cast<double>(R) : 0.0;
-  g->group_cells = mean_cells > 24 ? 8 : 4;
-  g->group_virtual = 16;
   return GIFT_OK;
 }
 
@@ -775,8 +848,6 @@ extern "C" gift_status gift_build_graph(const gift_graph_desc *d, void *stream,
   (void)hipGetDevice(&g->device);
   gift_status s;
   {
-    // algorithmic bytes: the netlist in, the graph out (structure, float64
-    // weights and degrees, values and diagonal per sigma)
     ProfScope ps(st, GIFT_PROF_BUILD, 0.0);
     s = build_impl(d, st, g);
   }

@@ -105,9 +105,10 @@ struct gift_graph {
   std::vector<gift::SigmaBlock> sig;
   int64_t bytes = 0;
   int device = 0;
-  // Row-split schedule of the SpMM (chosen at build time).
-  int32_t group_cells = 4;    // lanes per row for rows [0, N)
-  int32_t group_virtual = 16; // lanes per row for rows [N, R)
+  // Row tiles of the SpMM: tile t covers rows [tile_row[t], tile_row[t+1]).
+  int32_t *tile_row = nullptr;  // int32[num_tiles + 1]
+  int64_t num_tiles = 0;
+  int64_t num_tiles_cells = 0;  // tiles covering rows [0, N)
 };
 
 namespace gift {
@@ -130,6 +131,19 @@ gift_status prepare_sigma(gift_graph *g, double sigma, hipStream_t s);
 
 // Exclusive prefix sum: out[0..n] with out[n] = total (int64 output).
 gift_status scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, hipStream_t s);
+
+// Row tiles (see tiles.hip): a tile is a single row longer than kLongRow or
+// rows starting in one window of kTileEntries entries, at most kTileRows rows.
+constexpr int kTileEntries = 2048;
+constexpr int kTileRows = 512;
+constexpr int kLongRow = 256;
+constexpr int kTileCap = kTileEntries + kLongRow - 1;  // entries of a multi-row tile
+// tile_row must hold R + 1 entries; counts_dev[0] = number of tiles T,
+// counts_dev[1] = tiles that start before row `split`.
+gift_status build_tiles(const int32_t *off, int64_t R, int64_t split, hipStream_t st,
+                        int32_t *tile_row, int64_t *counts_dev);
+gift_status build_tiles64(const int64_t *off, int64_t R, int64_t split, hipStream_t st,
+                          int32_t *tile_row, int64_t *counts_dev);
 
 // ---------------------------------------------------------------------------
 // Storage types.  bf16 and f16 are stored as raw 16-bit patterns; values are

@@ -32,10 +32,7 @@ struct PassArgs {
   const void *diag;
   const void *x;
   void *y;
-  int64_t rows_a;    // rows [0, rows_a) use lanes_a lanes per row
-  int64_t rows_end;  // rows [rows_a, rows_end) use lanes_b lanes per row
-  int32_t lanes_a, lanes_b;
-  uint32_t blocks_a; // blocks covering segment a
+  const int32_t *tile_row;  // tiles [0, num_tiles) of this launch
 };
 
 struct FinalArgs {
@@ -70,60 +67,13 @@ __device__ __forceinline__ double load_in(const void *p, int32_t dt, int64_t i) 
                         : static_cast<double>(static_cast<const float *>(p)[i]);
 }
 
+// Writes row `row` of the pass result: the stored iterate, or (last pass) the
+// float64 combine of all terms in term order.
 template <int D, int C, bool kFinal>
-__global__ __launch_bounds__(kBlock) void k_spmm(PassArgs p, FinalArgs f) {
+__device__ __forceinline__ void emit_row(const PassArgs &p, const FinalArgs &f, int64_t row,
+                                         const typename Store<D>::A *acc) {
   using S = Store<D>;
   using T = typename S::T;
-  using A = typename S::A;
-  const uint32_t blk = xcd_remap(blockIdx.x, gridDim.x);
-  int64_t row;
-  int G;
-  if (blk < p.blocks_a) {
-    G = p.lanes_a;
-    row = static_cast<int64_t>(blk) * (kBlock / G) + threadIdx.x / G;
-    if (row >= p.rows_a) row = -1;
-  } else {
-    G = p.lanes_b;
-    row = p.rows_a + static_cast<int64_t>(blk - p.blocks_a) * (kBlock / G) + threadIdx.x / G;
-    if (row >= p.rows_end) row = -1;
-  }
-  const int lane = threadIdx.x & (G - 1);
-  const T *__restrict__ x = static_cast<const T *>(p.x);
-  const T *__restrict__ val = static_cast<const T *>(p.val);
-  const int32_t *__restrict__ col = p.col;
-  A acc[C];
-#pragma unroll
-  for (int c = 0; c < C; ++c) acc[c] = 0;
-  if (row >= 0) {
-    const int32_t p0 = p.row_ptr[row], p1 = p.row_ptr[row + 1];
-    int32_t q = p0 + lane;
-    for (; q + G < p1; q += 2 * G) {
-      const int32_t j0 = col[q], j1 = col[q + G];
-      const A v0 = S::load(val[q]), v1 = S::load(val[q + G]);
-      const auto x0 = load_row<T, C>(x, j0);
-      const auto x1 = load_row<T, C>(x, j1);
-#pragma unroll
-      for (int c = 0; c < C; ++c) acc[c] += v0 * S::load(x0.v[c]);
-#pragma unroll
-      for (int c = 0; c < C; ++c) acc[c] += v1 * S::load(x1.v[c]);
-    }
-    if (q < p1) {
-      const int32_t j0 = col[q];
-      const A v0 = S::load(val[q]);
-      const auto x0 = load_row<T, C>(x, j0);
-#pragma unroll
-      for (int c = 0; c < C; ++c) acc[c] += v0 * S::load(x0.v[c]);
-    }
-  }
-  for (int off = G >> 1; off > 0; off >>= 1) {
-#pragma unroll
-    for (int c = 0; c < C; ++c) acc[c] += __shfl_xor(acc[c], off);
-  }
-  if (row < 0 || lane != 0) return;
-  const A dg = static_cast<const A *>(p.diag)[row];
-  const auto xi = load_row<T, C>(x, row);
-#pragma unroll
-  for (int c = 0; c < C; ++c) acc[c] = acc[c] + dg * S::load(xi.v[c]);
   if constexpr (!kFinal) {
     typename SigRow<T, C>::V out;
 #pragma unroll
@@ -147,6 +97,183 @@ __global__ __launch_bounds__(kBlock) void k_spmm(PassArgs p, FinalArgs f) {
       const int64_t o = row * f.ld_out + f.col0 + c;
       if (f.out_dtype == GIFT_F64) static_cast<double *>(f.y_out)[o] = s;
       else static_cast<float *>(f.y_out)[o] = static_cast<float>(s);
+    }
+  }
+}
+
+// Lanes per row in the reduction of a tile with `rows` rows.
+__device__ __forceinline__ int lanes_for(int rows) {
+  int g = 1;
+  while (g < 64 && rows * g * 2 <= kBlock) g <<= 1;
+  return g;
+}
+
+// One SpMM pass over the tiles of this launch, one tile per block.
+//
+// Multi-row tile: all entries are fetched at once (coalesced col/value loads,
+// then the signal gathers, up to kStage per thread in flight), their products
+// staged in LDS, then each row is summed by a group of lanes sized to the
+// tile's row count.  When the products would not fit the LDS budget (wide
+// signal rows) the entries (col, value) are staged instead and the row groups
+// gather the signal themselves.  Single long row: the whole block strides
+// over the row and reduces across its waves.
+template <int D, int C, bool kFinal>
+__global__ __launch_bounds__(kBlock) void k_spmm(PassArgs p, FinalArgs f) {
+  using S = Store<D>;
+  using T = typename S::T;
+  using A = typename S::A;
+  constexpr bool kStageProducts = C * sizeof(A) <= 8;
+  constexpr int kStage = (kTileCap + kBlock - 1) / kBlock;
+  __shared__ int32_t loff[kTileRows + 1];
+  __shared__ A ldx[kStageProducts ? kTileRows * C : 1];
+  __shared__ A lprod[kStageProducts ? kTileCap * C : 1];
+  __shared__ int32_t lcol[kStageProducts ? 1 : kTileCap];
+  __shared__ A lval[kStageProducts ? 1 : kTileCap];
+  __shared__ A lred[kBlock / kWave][C];
+
+  const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int tid = threadIdx.x;
+  const int64_t r0 = p.tile_row[tile], r1 = p.tile_row[tile + 1];
+  const int64_t p0 = p.row_ptr[r0], p1 = p.row_ptr[r1];
+  const int nrows = static_cast<int>(r1 - r0);
+  const int64_t n = p1 - p0;
+  const T *__restrict__ x = static_cast<const T *>(p.x);
+  const T *__restrict__ val = static_cast<const T *>(p.val);
+  const int32_t *__restrict__ col = p.col;
+  const A *__restrict__ diag = static_cast<const A *>(p.diag);
+
+  if (nrows == 1 && n > kLongRow) {
+    // single long row
+    A acc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = 0;
+    int64_t q = p0 + tid;
+    for (; q + 3 * kBlock < p1; q += 4 * kBlock) {
+      int32_t j[4];
+      A v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        j[u] = col[q + u * kBlock];
+        v[u] = S::load(val[q + u * kBlock]);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const auto xr = load_row<T, C>(x, j[u]);
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[c] += v[u] * S::load(xr.v[c]);
+      }
+    }
+    for (; q < p1; q += kBlock) {
+      const auto xr = load_row<T, C>(x, col[q]);
+      const A v = S::load(val[q]);
+#pragma unroll
+      for (int c = 0; c < C; ++c) acc[c] += v * S::load(xr.v[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      for (int off = kWave / 2; off > 0; off >>= 1) acc[c] += __shfl_xor(acc[c], off);
+      if ((tid & (kWave - 1)) == 0) lred[tid / kWave][c] = acc[c];
+    }
+    __syncthreads();
+    if (tid == 0) {
+      A tot[C];
+      const A dg = diag[r0];
+      const auto xi = load_row<T, C>(x, r0);
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        A s = lred[0][c];
+        for (int w = 1; w < kBlock / kWave; ++w) s += lred[w][c];
+        tot[c] = s + dg * S::load(xi.v[c]);
+      }
+      emit_row<D, C, kFinal>(p, f, r0, tot);
+    }
+    return;
+  }
+
+  // ---- multi-row tile (n <= kTileCap)
+  {
+    int32_t jj[kStage];
+    A vv[kStage];
+#pragma unroll
+    for (int k = 0; k < kStage; ++k) {
+      const int i = tid + k * kBlock;
+      jj[k] = 0;
+      vv[k] = 0;
+      if (i < n) {
+        jj[k] = col[p0 + i];
+        vv[k] = S::load(val[p0 + i]);
+      }
+    }
+    if constexpr (kStageProducts) {
+#pragma unroll
+      for (int k = 0; k < kStage; ++k) {
+        const int i = tid + k * kBlock;
+        if (i < n) {
+          const auto xr = load_row<T, C>(x, jj[k]);
+#pragma unroll
+          for (int c = 0; c < C; ++c) lprod[i * C + c] = vv[k] * S::load(xr.v[c]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < kStage; ++k) {
+        const int i = tid + k * kBlock;
+        if (i < n) {
+          lcol[i] = jj[k];
+          lval[i] = vv[k];
+        }
+      }
+    }
+  }
+  for (int i = tid; i <= nrows; i += kBlock) loff[i] = static_cast<int32_t>(p.row_ptr[r0 + i] - p0);
+  if constexpr (kStageProducts) {
+    for (int i = tid; i < nrows; i += kBlock) {
+      const A dg = diag[r0 + i];
+      const auto xi = load_row<T, C>(x, r0 + i);
+#pragma unroll
+      for (int c = 0; c < C; ++c) ldx[i * C + c] = dg * S::load(xi.v[c]);
+    }
+  }
+  __syncthreads();
+
+  const int G = lanes_for(nrows);
+  const int lane = tid & (G - 1);
+  const int groups = kBlock / G;
+  for (int base = 0; base < nrows; base += groups) {
+    const int rr = base + tid / G;
+    const bool live = rr < nrows;
+    A acc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = 0;
+    if (live) {
+      const int q1 = loff[rr + 1];
+      for (int q = loff[rr] + lane; q < q1; q += G) {
+        if constexpr (kStageProducts) {
+#pragma unroll
+          for (int c = 0; c < C; ++c) acc[c] += lprod[q * C + c];
+        } else {
+          const auto xr = load_row<T, C>(x, lcol[q]);
+          const A v = lval[q];
+#pragma unroll
+          for (int c = 0; c < C; ++c) acc[c] += v * S::load(xr.v[c]);
+        }
+      }
+    }
+    for (int off = G >> 1; off > 0; off >>= 1) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) acc[c] += __shfl_xor(acc[c], off);
+    }
+    if (live && lane == 0) {
+      if constexpr (kStageProducts) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[c] = acc[c] + ldx[rr * C + c];
+      } else {
+        const A dg = diag[r0 + rr];
+        const auto xi = load_row<T, C>(x, r0 + rr);
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[c] = acc[c] + dg * S::load(xi.v[c]);
+      }
+      emit_row<D, C, kFinal>(p, f, r0 + rr, acc);
     }
   }
 }
@@ -263,7 +390,6 @@ gift_status run_chunk(const gift_graph *g, const std::vector<Group> &groups,
     fa.alpha[t] = terms[t].alpha;
   }
 
-  const int32_t ga = g->group_cells, gb = g->group_virtual;
   for (size_t gi = 0; gi < groups.size(); ++gi) {
     const Group &grp = groups[gi];
     const T *cur = x0;
@@ -282,14 +408,10 @@ gift_status run_chunk(const gift_graph *g, const std::vector<Group> &groups,
       pa.diag = grp.blk->diag;
       pa.x = cur;
       pa.y = dst;
-      pa.rows_a = N;
-      pa.rows_end = fin ? N : R;
-      pa.lanes_a = ga;
-      pa.lanes_b = gb;
-      pa.blocks_a = static_cast<uint32_t>((N + (kBlock / ga) - 1) / (kBlock / ga));
-      int64_t blocks_b = (pa.rows_end - N + (kBlock / gb) - 1) / (kBlock / gb);
-      unsigned grid = static_cast<unsigned>(pa.blocks_a + blocks_b);
-      if (grid == 0) continue;
+      pa.tile_row = g->tile_row;
+      const int64_t tiles = fin ? g->num_tiles_cells : g->num_tiles;
+      if (tiles == 0) continue;
+      const unsigned grid = static_cast<unsigned>(tiles);
       {
         ProfScope ps(st, fin ? GIFT_PROF_SPMM_FINAL : GIFT_PROF_SPMM,
                      pass_bytes<D, C>(g, fin, nt, out_dt));
