@@ -173,8 +173,8 @@ gift_status gift_build_graph(const gift_graph_desc *desc, void *stream, gift_gra
  * Powers are formed by repeated sparse products per distinct sigma; virtual
  * rows start at the mean of their net's cells.  The terms are combined in
  * float64 in the given order and rounded once to out_dtype.  Asynchronous on
- * `stream`; device scratch is taken from and returned to the stream-ordered
- * allocator.  Errors: GIFT_EINVAL (NULL pointers, sizes, order < 1, a sigma
+ * `stream`; device scratch comes from the library's stream-ordered cache
+ * (see gift_memory_stats).  Errors: GIFT_EINVAL (NULL pointers, sizes, order < 1, a sigma
  * not prepared), GIFT_EUNSUPPORTED (dtype), GIFT_ENOMEM, GIFT_EDEVICE.
  */
 gift_status gift_filter_placement(const gift_graph *graph, const gift_term *terms,
@@ -246,6 +246,18 @@ gift_status gift_profile_collect(int32_t prof_class, int64_t *launches, double *
 /* ------------------------------------------------------------------------
  * Misc.
  * ----------------------------------------------------------------------*/
+
+/*
+ * Device memory held by the library's caching allocator: every block it
+ * obtained from the runtime (cached or in use) and the part in use by graphs,
+ * batches and in-flight calls.  Blocks freed on a stream are reused only for
+ * that stream, so the cache never needs a device synchronisation to reuse.
+ */
+gift_status gift_memory_stats(int64_t *bytes_held, int64_t *bytes_in_use);
+
+/* Return every cached (unused) block to the runtime.  Synchronises the
+ * device first.  Memory in use is not affected. */
+gift_status gift_release_cached_memory(void);
 
 const char *gift_status_string(gift_status status);
 

@@ -86,6 +86,8 @@ SIGNATURES = {
     "gift_profile_enable": (C.c_int, [C.c_int32]),
     "gift_profile_collect": (C.c_int, [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                        C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "gift_memory_stats": (C.c_int, [C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "gift_release_cached_memory": (C.c_int, []),
     "gift_status_string": (C.c_char_p, [C.c_int]),
     "gift_last_error": (C.c_char_p, []),
     "gift_abi_version": (C.c_int32, []),

@@ -2,6 +2,9 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <unordered_map>
 
 #include "common.h"
 
@@ -30,10 +33,69 @@ gift_status check_launch(const char *what) {
   return GIFT_OK;
 }
 
+namespace {
+
+// Stream-ordered caching allocator.  Device memory comes from hipMalloc in
+// blocks that are never returned to the runtime while cached: a freed block
+// goes back to the free list of the stream it was freed on and is handed out
+// again only for work on that same stream, so stream order alone makes the
+// reuse safe (the previous user's kernels precede the new user's).  A free
+// block is reused for a request when it is at most 25% larger.  This keeps
+// the runtime's allocation calls (tens of microseconds each, more for large
+// frees) off the build and filter paths.
+struct Block {
+  void *ptr;
+  size_t size;
+};
+
+struct Pool {
+  std::mutex m;
+  // per (device, stream): free blocks by size
+  std::map<std::pair<int, hipStream_t>, std::multimap<size_t, void *>> free_lists;
+  std::unordered_map<void *, std::pair<size_t, int>> live;  // ptr -> (size, device)
+  int64_t bytes_held = 0;   // all blocks, cached or in use
+  int64_t bytes_in_use = 0;
+};
+
+Pool &pool() {
+  static Pool *p = new Pool();  // outlives static destructors of callers
+  return *p;
+}
+
+size_t round_size(size_t n) {
+  if (n < 256) return 256;
+  if (n < (size_t(2) << 20)) return (n + 255) & ~size_t(255);
+  return (n + (size_t(2) << 20) - 1) & ~((size_t(2) << 20) - 1);
+}
+
+}  // namespace
+
 gift_status dev_alloc(void **p, size_t bytes, hipStream_t s, const char *what) {
   *p = nullptr;
-  if (bytes == 0) bytes = 16;
-  hipError_t e = hipMallocAsync(p, bytes, s);
+  const size_t need = round_size(bytes == 0 ? 16 : bytes);
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  Pool &pl = pool();
+  {
+    std::lock_guard<std::mutex> lk(pl.m);
+    auto &fl = pl.free_lists[{dev, s}];
+    auto it = fl.lower_bound(need);
+    if (it != fl.end() && it->first <= need + need / 4) {
+      *p = it->second;
+      pl.live[it->second] = {it->first, dev};
+      pl.bytes_in_use += static_cast<int64_t>(it->first);
+      fl.erase(it);
+      return GIFT_OK;
+    }
+  }
+  hipError_t e = hipMalloc(p, need);
+  if (e != hipSuccess) {
+    // drop this device's cached blocks and retry once
+    (void)hipGetLastError();
+    gift_status st = release_cached(dev);
+    if (st != GIFT_OK) return st;
+    e = hipMalloc(p, need);
+  }
   if (e != hipSuccess) {
     *p = nullptr;
     (void)hipGetLastError();
@@ -41,11 +103,55 @@ gift_status dev_alloc(void **p, size_t bytes, hipStream_t s, const char *what) {
                      "device allocation of %zu bytes for %s failed: %s", bytes, what,
                      hipGetErrorString(e));
   }
+  std::lock_guard<std::mutex> lk(pl.m);
+  pl.live[*p] = {need, dev};
+  pl.bytes_held += static_cast<int64_t>(need);
+  pl.bytes_in_use += static_cast<int64_t>(need);
   return GIFT_OK;
 }
 
 void dev_free(void *p, hipStream_t s) {
-  if (p) (void)hipFreeAsync(p, s);
+  if (!p) return;
+  Pool &pl = pool();
+  std::lock_guard<std::mutex> lk(pl.m);
+  auto it = pl.live.find(p);
+  if (it == pl.live.end()) return;
+  const size_t size = it->second.first;
+  const int dev = it->second.second;
+  pl.live.erase(it);
+  pl.bytes_in_use -= static_cast<int64_t>(size);
+  pl.free_lists[{dev, s}].emplace(size, p);
+}
+
+gift_status release_cached(int dev) {
+  Pool &pl = pool();
+  std::vector<void *> drop;
+  {
+    std::lock_guard<std::mutex> lk(pl.m);
+    for (auto it = pl.free_lists.begin(); it != pl.free_lists.end();) {
+      if (dev >= 0 && it->first.first != dev) {
+        ++it;
+        continue;
+      }
+      for (auto &kv : it->second) {
+        drop.push_back(kv.second);
+        pl.bytes_held -= static_cast<int64_t>(kv.first);
+      }
+      it = pl.free_lists.erase(it);
+    }
+  }
+  if (drop.empty()) return GIFT_OK;
+  // blocks may still be referenced by queued work on their streams
+  GIFT_HIP(hipDeviceSynchronize());
+  for (void *q : drop) GIFT_HIP(hipFree(q));
+  return GIFT_OK;
+}
+
+void pool_stats(int64_t *held, int64_t *in_use) {
+  Pool &pl = pool();
+  std::lock_guard<std::mutex> lk(pl.m);
+  if (held) *held = pl.bytes_held;
+  if (in_use) *in_use = pl.bytes_in_use;
 }
 
 const SigmaBlock *find_sigma(const gift_graph *g, double sigma) {
@@ -75,6 +181,17 @@ const char *gift_status_string(gift_status s) {
 const char *gift_last_error(void) { return t_last_error.c_str(); }
 
 int32_t gift_abi_version(void) { return GIFT_ABI_VERSION; }
+
+gift_status gift_memory_stats(int64_t *bytes_held, int64_t *bytes_in_use) {
+  clear_error();
+  pool_stats(bytes_held, bytes_in_use);
+  return GIFT_OK;
+}
+
+gift_status gift_release_cached_memory(void) {
+  clear_error();
+  return release_cached(-1);
+}
 
 gift_status gift_graph_get_info(const gift_graph *g, gift_graph_info *info) {
   clear_error();
@@ -118,6 +235,7 @@ gift_status gift_destroy_graph(gift_graph *g, void *stream) {
   dev_free(g->w, s);
   dev_free(g->deg, s);
   dev_free(g->tile_row, s);
+  dev_free(g->tile_ptr, s);
   for (SigmaBlock &b : g->sig) {
     dev_free(b.val, s);
     dev_free(b.diag, s);

@@ -371,6 +371,12 @@ __global__ void k_row_ptr32(const int64_t *rp64, int64_t n, int32_t *rp32) {
   if (i <= n) rp32[i] = static_cast<int32_t>(rp64[i]);
 }
 
+__global__ void k_tile_ptr(const int32_t *tile_row, const int64_t *rp64, int64_t T,
+                           int32_t *tile_ptr) {
+  int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t <= T) tile_ptr[t] = static_cast<int32_t>(rp64[tile_row[t]]);
+}
+
 // ---------------------------------------------------------------------------
 // 6. merge into the CSR of A, degrees
 // ---------------------------------------------------------------------------
@@ -793,6 +799,12 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
   g->bytes = (R + 1) * 4 + nnz * 12 + R * 8 + (R + 2) * 4;
   k_row_ptr32<<<grid_for(R + 1), kBlock, 0, st>>>(rp64, R, g->row_ptr);
   GIFT_TRY(check_launch("k_row_ptr32"));
+  GIFT_TRY(dev_alloc(reinterpret_cast<void **>(&g->tile_ptr), (g->num_tiles + 1) * 4, st,
+                     "tile entry offsets"));
+  g->bytes += (g->num_tiles + 1) * 4;
+  k_tile_ptr<<<grid_for(g->num_tiles + 1), kBlock, 0, st>>>(g->tile_row, rp64, g->num_tiles,
+                                                             g->tile_ptr);
+  GIFT_TRY(check_launch("k_tile_ptr"));
 
   // 6. merge
   if (num_row_tiles > 0) {

@@ -52,12 +52,15 @@ class ProfScope {
 };
 
 // ---------------------------------------------------------------------------
-// Device memory: stream-ordered allocations (hipMallocAsync / hipFreeAsync),
-// so that building, filtering and releasing graphs on different streams does
-// not serialise the device.
+// Device memory: a stream-ordered caching allocator (see api.hip).  A block
+// freed on stream s is reused only by later allocations for stream s.
 // ---------------------------------------------------------------------------
 gift_status dev_alloc(void **p, size_t bytes, hipStream_t s, const char *what);
 void dev_free(void *p, hipStream_t s);
+// Returns the cached (free) blocks of device `dev` (all devices if < 0) to
+// the runtime; synchronises the device first.
+gift_status release_cached(int dev);
+void pool_stats(int64_t *held, int64_t *in_use);
 
 // RAII holder for build/filter scratch, released in stream order.
 struct Scratch {
@@ -107,6 +110,7 @@ struct gift_graph {
   int device = 0;
   // Row tiles of the SpMM: tile t covers rows [tile_row[t], tile_row[t+1]).
   int32_t *tile_row = nullptr;  // int32[num_tiles + 1]
+  int32_t *tile_ptr = nullptr;  // int32[num_tiles + 1]: row_ptr[tile_row[t]]
   int64_t num_tiles = 0;
   int64_t num_tiles_cells = 0;  // tiles covering rows [0, N)
 };

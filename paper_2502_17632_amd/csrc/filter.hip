@@ -33,6 +33,7 @@ struct PassArgs {
   const void *x;
   void *y;
   const int32_t *tile_row;  // tiles [0, num_tiles) of this launch
+  const int32_t *tile_ptr;  // first entry of every tile
 };
 
 struct FinalArgs {
@@ -134,7 +135,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm(PassArgs p, FinalArgs f) {
   const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x);
   const int tid = threadIdx.x;
   const int64_t r0 = p.tile_row[tile], r1 = p.tile_row[tile + 1];
-  const int64_t p0 = p.row_ptr[r0], p1 = p.row_ptr[r1];
+  const int64_t p0 = p.tile_ptr[tile], p1 = p.tile_ptr[tile + 1];
   const int nrows = static_cast<int>(r1 - r0);
   const int64_t n = p1 - p0;
   const T *__restrict__ x = static_cast<const T *>(p.x);
@@ -191,27 +192,57 @@ __global__ __launch_bounds__(kBlock) void k_spmm(PassArgs p, FinalArgs f) {
   }
 
   // ---- multi-row tile (n <= kTileCap)
+  // Every load is issued unconditionally (inactive slots read entry p0 or
+  // row 0, always valid) so that all of a thread's loads are in flight at
+  // once: first col/value and the rows' offsets and diagonal terms, then the
+  // signal gathers; only then are results written to LDS.
   {
     int32_t jj[kStage];
     A vv[kStage];
 #pragma unroll
     for (int k = 0; k < kStage; ++k) {
       const int i = tid + k * kBlock;
-      jj[k] = 0;
-      vv[k] = 0;
-      if (i < n) {
-        jj[k] = col[p0 + i];
-        vv[k] = S::load(val[p0 + i]);
+      const int64_t q = i < n ? p0 + i : 0;
+      jj[k] = col[q];
+      vv[k] = S::load(val[q]);
+    }
+    constexpr int kRowIters = (kTileRows + 1 + kBlock - 1) / kBlock;
+    int32_t ro[kRowIters];
+#pragma unroll
+    for (int k = 0; k < kRowIters; ++k) {
+      const int i = tid + k * kBlock;
+      ro[k] = p.row_ptr[i <= nrows ? r0 + i : r0];
+    }
+    constexpr int kDiagIters = kTileRows / kBlock;
+    A dg[kDiagIters];
+    typename SigRow<T, C>::V xr_row[kDiagIters];
+    if constexpr (kStageProducts) {
+#pragma unroll
+      for (int k = 0; k < kDiagIters; ++k) {
+        const int i = tid + k * kBlock;
+        const int64_t r = i < nrows ? r0 + i : r0;
+        dg[k] = diag[r];
+        xr_row[k] = load_row<T, C>(x, r);
       }
     }
     if constexpr (kStageProducts) {
+      typename SigRow<T, C>::V xv[kStage];
+#pragma unroll
+      for (int k = 0; k < kStage; ++k) xv[k] = load_row<T, C>(x, jj[k]);
 #pragma unroll
       for (int k = 0; k < kStage; ++k) {
         const int i = tid + k * kBlock;
         if (i < n) {
-          const auto xr = load_row<T, C>(x, jj[k]);
 #pragma unroll
-          for (int c = 0; c < C; ++c) lprod[i * C + c] = vv[k] * S::load(xr.v[c]);
+          for (int c = 0; c < C; ++c) lprod[i * C + c] = vv[k] * S::load(xv[k].v[c]);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kDiagIters; ++k) {
+        const int i = tid + k * kBlock;
+        if (i < nrows) {
+#pragma unroll
+          for (int c = 0; c < C; ++c) ldx[i * C + c] = dg[k] * S::load(xr_row[k].v[c]);
         }
       }
     } else {
@@ -224,14 +255,10 @@ __global__ __launch_bounds__(kBlock) void k_spmm(PassArgs p, FinalArgs f) {
         }
       }
     }
-  }
-  for (int i = tid; i <= nrows; i += kBlock) loff[i] = static_cast<int32_t>(p.row_ptr[r0 + i] - p0);
-  if constexpr (kStageProducts) {
-    for (int i = tid; i < nrows; i += kBlock) {
-      const A dg = diag[r0 + i];
-      const auto xi = load_row<T, C>(x, r0 + i);
 #pragma unroll
-      for (int c = 0; c < C; ++c) ldx[i * C + c] = dg * S::load(xi.v[c]);
+    for (int k = 0; k < kRowIters; ++k) {
+      const int i = tid + k * kBlock;
+      if (i <= nrows) loff[i] = static_cast<int32_t>(ro[k] - p0);
     }
   }
   __syncthreads();
@@ -247,15 +274,27 @@ __global__ __launch_bounds__(kBlock) void k_spmm(PassArgs p, FinalArgs f) {
     for (int c = 0; c < C; ++c) acc[c] = 0;
     if (live) {
       const int q1 = loff[rr + 1];
-      for (int q = loff[rr] + lane; q < q1; q += G) {
-        if constexpr (kStageProducts) {
+      if constexpr (kStageProducts) {
+        for (int q = loff[rr] + lane; q < q1; q += G) {
 #pragma unroll
           for (int c = 0; c < C; ++c) acc[c] += lprod[q * C + c];
-        } else {
-          const auto xr = load_row<T, C>(x, lcol[q]);
-          const A v = lval[q];
+        }
+      } else {
+        int q = loff[rr] + lane;
+        for (; q + G < q1; q += 2 * G) {
+          const auto xa = load_row<T, C>(x, lcol[q]);
+          const auto xb = load_row<T, C>(x, lcol[q + G]);
+          const A va = lval[q], vb = lval[q + G];
 #pragma unroll
-          for (int c = 0; c < C; ++c) acc[c] += v * S::load(xr.v[c]);
+          for (int c = 0; c < C; ++c) acc[c] += va * S::load(xa.v[c]);
+#pragma unroll
+          for (int c = 0; c < C; ++c) acc[c] += vb * S::load(xb.v[c]);
+        }
+        if (q < q1) {
+          const auto xa = load_row<T, C>(x, lcol[q]);
+          const A va = lval[q];
+#pragma unroll
+          for (int c = 0; c < C; ++c) acc[c] += va * S::load(xa.v[c]);
         }
       }
     }
@@ -409,6 +448,7 @@ gift_status run_chunk(const gift_graph *g, const std::vector<Group> &groups,
       pa.x = cur;
       pa.y = dst;
       pa.tile_row = g->tile_row;
+      pa.tile_ptr = g->tile_ptr;
       const int64_t tiles = fin ? g->num_tiles_cells : g->num_tiles;
       if (tiles == 0) continue;
       const unsigned grid = static_cast<unsigned>(tiles);
