@@ -41,11 +41,18 @@ namespace {
 
 enum : uint32_t { kFlagBadNetPtr = 1u, kFlagBadPin = 2u };
 
-constexpr int kNetSortCap = 8192;  // longest net sorted in LDS (32-bit keys)
-constexpr int kRowSortCap = 4096;  // longest row sorted in LDS (64-bit keys, 32 KB)
-constexpr int kChunk32 = 8192;     // LDS chunk of the global merge sort (u32)
-constexpr int kChunk64 = 4096;     // LDS chunk of the global merge sort (u64)
-constexpr int kSmemBytes = 46 * 1024;
+// Tiles of the build kernels: smaller than the SpMM's so that the LDS each
+// block stages (keys, offsets, segment ids, merged weights) stays small and
+// many blocks share a CU.
+constexpr int kBTileEntries = 1024;
+constexpr int kBTileRows = 256;
+constexpr int kBLongRow = 128;
+constexpr int kBTileCap = kBTileEntries + kBLongRow - 1;
+constexpr TileShape kBuildTiles{kBTileEntries, kBTileRows, kBLongRow};
+constexpr int kNetSortCap = 2048;  // longest net sorted in LDS (32-bit keys, 8 KB)
+constexpr int kRowSortCap = 2048;  // longest row sorted in LDS (64-bit keys, 16 KB)
+constexpr int kChunk32 = 2048;     // LDS chunk of the global merge sort (u32)
+constexpr int kChunk64 = 2048;     // LDS chunk of the global merge sort (u64)
 
 __device__ __forceinline__ double clique_weight(int64_t m, int model) {
   return model == GIFT_W_TWO_OVER_M ? 2.0 / static_cast<double>(m)
@@ -112,7 +119,7 @@ __device__ __forceinline__ int64_t write_distinct(const uint32_t *src, int64_t n
   return base;
 }
 
-// A net longer than kLongRow pins, alone in its tile.
+// A net longer than kBLongRow pins, alone in its tile.
 __device__ __forceinline__ void net_long(const NetArgs &a, int64_t e, int64_t lo, int64_t n,
                                          unsigned char *smem) {
   uint32_t *keys = reinterpret_cast<uint32_t *>(smem);
@@ -157,22 +164,27 @@ __device__ __forceinline__ void net_long(const NetArgs &a, int64_t e, int64_t lo
   }
 }
 
+constexpr int kNetSmem = 10 * 1024;
+static_assert((kBTileCap + 1) * 4 + (kBTileRows + 2) * 4 + (kBTileCap + 1) * 2 + kBTileCap <= kNetSmem,
+              "net tile LDS");
+static_assert(kNetSortCap * 4 <= kNetSmem && kChunk32 * 4 <= kNetSmem, "long net LDS");
+
 __global__ __launch_bounds__(kBlock) void k_net_tiles(NetArgs a) {
-  __shared__ __attribute__((aligned(16))) unsigned char smem[kSmemBytes];
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kNetSmem];
   __shared__ int bad_s;
   const int64_t e0 = a.tiles[blockIdx.x], e1 = a.tiles[blockIdx.x + 1];
   const int64_t q0 = a.net_ptr[e0], q1 = a.net_ptr[e1];
   const int ns = static_cast<int>(e1 - e0);
   const int64_t n64 = q1 - q0;
-  if (ns == 1 && n64 > kLongRow) {
+  if (ns == 1 && n64 > kBLongRow) {
     net_long(a, e0, q0, n64, smem);
     return;
   }
-  const int n = static_cast<int>(n64);  // <= kTileCap
+  const int n = static_cast<int>(n64);  // <= kBTileCap
   uint32_t *key = reinterpret_cast<uint32_t *>(smem);
-  int32_t *loff = reinterpret_cast<int32_t *>(key + kTileCap + 1);
-  uint16_t *seg = reinterpret_cast<uint16_t *>(loff + kTileRows + 2);
-  uint8_t *first = reinterpret_cast<uint8_t *>(seg + kTileCap + 1);
+  int32_t *loff = reinterpret_cast<int32_t *>(key + kBTileCap + 1);
+  uint16_t *seg = reinterpret_cast<uint16_t *>(loff + kBTileRows + 2);
+  uint8_t *first = reinterpret_cast<uint8_t *>(seg + kBTileCap + 1);
   if (threadIdx.x == 0) bad_s = 0;
   __syncthreads();
   for (int k = threadIdx.x; k <= ns; k += kBlock) loff[k] = static_cast<int32_t>(a.net_ptr[e0 + k] - q0);
@@ -296,14 +308,20 @@ __device__ int32_t count_heads_block(const uint64_t *k, int64_t n, int32_t *tmp)
   return block_sum<int32_t>(heads, tmp);
 }
 
+constexpr int kSortSmem = 16 * 1024;
+static_assert((kBTileCap + 1) * 8 + (kBTileRows + 2) * 4 + (kBTileCap + 1) * 2 + kBTileCap <=
+                  kSortSmem,
+              "row sort LDS");
+static_assert(kRowSortCap * 8 <= kSortSmem && kChunk64 * 8 <= kSortSmem, "long row LDS");
+
 __global__ __launch_bounds__(kBlock) void k_row_sort_tiles(RowArgs a) {
-  __shared__ __attribute__((aligned(16))) unsigned char smem[kSmemBytes];
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kSortSmem];
   __shared__ int32_t tmp[kBlock / kWave];
   const int64_t r0 = a.tiles[blockIdx.x], r1 = a.tiles[blockIdx.x + 1];
   const int64_t z0 = a.zoff[r0], z1 = a.zoff[r1];
   const int ns = static_cast<int>(r1 - r0);
   const int64_t n64 = z1 - z0;
-  if (ns == 1 && n64 > kLongRow) {
+  if (ns == 1 && n64 > kBLongRow) {
     uint64_t *keys = reinterpret_cast<uint64_t *>(smem);
     int32_t total;
     if (n64 <= kRowSortCap) {
@@ -326,9 +344,9 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_tiles(RowArgs a) {
   }
   const int n = static_cast<int>(n64);
   uint64_t *key = reinterpret_cast<uint64_t *>(smem);
-  int32_t *loff = reinterpret_cast<int32_t *>(key + kTileCap + 1);
-  uint16_t *seg = reinterpret_cast<uint16_t *>(loff + kTileRows + 2);
-  uint8_t *head = reinterpret_cast<uint8_t *>(seg + kTileCap + 1);
+  int32_t *loff = reinterpret_cast<int32_t *>(key + kBTileCap + 1);
+  uint16_t *seg = reinterpret_cast<uint16_t *>(loff + kBTileRows + 2);
+  uint8_t *head = reinterpret_cast<uint8_t *>(seg + kBTileCap + 1);
   for (int k = threadIdx.x; k <= ns; k += kBlock) loff[k] = static_cast<int32_t>(a.zoff[r0 + k] - z0);
   for (int i = threadIdx.x; i < n; i += kBlock) key[i] = a.zkey[z0 + i];
   __syncthreads();
@@ -401,15 +419,19 @@ __device__ __forceinline__ double run_weight(const uint64_t *k, int64_t i, int64
   return s;
 }
 
+constexpr int kMergeSmem = 23 * 1024;
+static_assert((kBTileCap + 1) * 16 + 2 * (kBTileRows + 2) * 4 + (kBTileCap + 1) * 2 <= kMergeSmem,
+              "row merge LDS");
+
 __global__ __launch_bounds__(kBlock) void k_row_merge_tiles(MergeArgs a) {
-  __shared__ __attribute__((aligned(16))) unsigned char smem[kSmemBytes];
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kMergeSmem];
   __shared__ int32_t tmp[kBlock / kWave];
   const int64_t r0 = a.tiles[blockIdx.x], r1 = a.tiles[blockIdx.x + 1];
   const int64_t z0 = a.zoff[r0], z1 = a.zoff[r1];
   const int ns = static_cast<int>(r1 - r0);
   const int64_t n64 = z1 - z0;
   const int64_t o0 = a.row_ptr[r0];
-  if (ns == 1 && n64 > kLongRow) {
+  if (ns == 1 && n64 > kBLongRow) {
     // one long row: chunks of kBlock keys straight from global memory
     const uint64_t *k = a.zsort + z0;
     double *mw = reinterpret_cast<double *>(smem);
@@ -428,7 +450,7 @@ __global__ __launch_bounds__(kBlock) void k_row_merge_tiles(MergeArgs a) {
     __syncthreads();
     // degree: ascending column, staged through LDS in chunks
     double d = 0.0;
-    constexpr int kChunk = kSmemBytes / 8;
+    constexpr int kChunk = kMergeSmem / 8;
     for (int64_t c0 = 0; c0 < base; c0 += kChunk) {
       const int len = static_cast<int>(base - c0 < kChunk ? base - c0 : kChunk);
       for (int i = threadIdx.x; i < len; i += kBlock) mw[i] = a.w[o0 + c0 + i];
@@ -442,10 +464,10 @@ __global__ __launch_bounds__(kBlock) void k_row_merge_tiles(MergeArgs a) {
   }
   const int n = static_cast<int>(n64);
   uint64_t *key = reinterpret_cast<uint64_t *>(smem);
-  double *mw = reinterpret_cast<double *>(key + kTileCap + 1);
-  int32_t *loff = reinterpret_cast<int32_t *>(mw + kTileCap + 1);
-  int32_t *moff = loff + kTileRows + 2;
-  uint16_t *seg = reinterpret_cast<uint16_t *>(moff + kTileRows + 2);
+  double *mw = reinterpret_cast<double *>(key + kBTileCap + 1);
+  int32_t *loff = reinterpret_cast<int32_t *>(mw + kBTileCap + 1);
+  int32_t *moff = loff + kBTileRows + 2;
+  uint16_t *seg = reinterpret_cast<uint16_t *>(moff + kBTileRows + 2);
   for (int k = threadIdx.x; k <= ns; k += kBlock) {
     loff[k] = static_cast<int32_t>(a.zoff[r0 + k] - z0);
     moff[k] = static_cast<int32_t>(a.row_ptr[r0 + k] - o0);
@@ -456,7 +478,7 @@ __global__ __launch_bounds__(kBlock) void k_row_merge_tiles(MergeArgs a) {
   __syncthreads();
   // each thread owns a contiguous chunk of entries; heads are numbered by a
   // block scan, which also numbers the merged entries of the tile in order
-  constexpr int kPer = (kTileCap + kBlock - 1) / kBlock;
+  constexpr int kPer = (kBTileCap + kBlock - 1) / kBlock;
   const int b = threadIdx.x * kPer;
   int mine = 0;
   for (int i = b; i < b + kPer && i < n; ++i)
@@ -684,7 +706,7 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
   int64_t *net_tile_counts = nullptr;
   GIFT_TRY(sc.get(&net_tiles, E + 2, "net tiles"));
   GIFT_TRY(sc.get(&net_tile_counts, 2, "net tile counts"));
-  GIFT_TRY(build_tiles64(net_ptr, E, E, st, net_tiles, net_tile_counts));
+  GIFT_TRY(build_tiles64(net_ptr, E, E, kBuildTiles, st, net_tiles, net_tile_counts));
   int64_t num_net_tiles = 0;
   {
     const int64_t *ptrs[1] = {net_tile_counts};
@@ -732,7 +754,7 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
   k_count<<<grid_for(P), kBlock, 0, st>>>(ea, cnt);
   GIFT_TRY(check_launch("k_count"));
   GIFT_TRY(scan_i32_to_i64(cnt, zoff, N, st));
-  GIFT_TRY(build_tiles64(zoff, N, N, st, row_tiles, row_tile_counts));
+  GIFT_TRY(build_tiles64(zoff, N, N, kBuildTiles, st, row_tiles, row_tile_counts));
   k_flag_to_i64<<<1, 1, 0, st>>>(flag, flag64);
   GIFT_TRY(check_launch("k_flag_to_i64"));
 
@@ -779,7 +801,7 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
   int64_t *tile_counts = nullptr;
   GIFT_TRY(dev_alloc(reinterpret_cast<void **>(&g->tile_row), (R + 2) * 4, st, "row tiles"));
   GIFT_TRY(sc.get(&tile_counts, 2, "tile counts"));
-  GIFT_TRY(build_tiles64(rp64, R, N, st, g->tile_row, tile_counts));
+  GIFT_TRY(build_tiles64(rp64, R, N, kSpmmTiles, st, g->tile_row, tile_counts));
   int64_t h2[4] = {0, 0, 0, 0};
   {
     const int64_t *ptrs[4] = {rp64 + R, rp64 + N, tile_counts, tile_counts + 1};

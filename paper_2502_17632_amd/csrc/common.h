@@ -136,18 +136,21 @@ gift_status prepare_sigma(gift_graph *g, double sigma, hipStream_t s);
 // Exclusive prefix sum: out[0..n] with out[n] = total (int64 output).
 gift_status scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, hipStream_t s);
 
-// Row tiles (see tiles.hip): a tile is a single row longer than kLongRow or
-// rows starting in one window of kTileEntries entries, at most kTileRows rows.
+// Row tiles (see tiles.hip): a tile is a single row longer than long_row or
+// rows starting in one window of `entries` entries, at most `rows` rows.
+struct TileShape {
+  int32_t entries, rows, long_row;
+};
+// The SpMM's tiles.
 constexpr int kTileEntries = 2048;
 constexpr int kTileRows = 512;
 constexpr int kLongRow = 256;
 constexpr int kTileCap = kTileEntries + kLongRow - 1;  // entries of a multi-row tile
+constexpr TileShape kSpmmTiles{kTileEntries, kTileRows, kLongRow};
 // tile_row must hold R + 1 entries; counts_dev[0] = number of tiles T,
 // counts_dev[1] = tiles that start before row `split`.
-gift_status build_tiles(const int32_t *off, int64_t R, int64_t split, hipStream_t st,
-                        int32_t *tile_row, int64_t *counts_dev);
-gift_status build_tiles64(const int64_t *off, int64_t R, int64_t split, hipStream_t st,
-                          int32_t *tile_row, int64_t *counts_dev);
+gift_status build_tiles64(const int64_t *off, int64_t R, int64_t split, TileShape sh,
+                          hipStream_t st, int32_t *tile_row, int64_t *counts_dev);
 
 // ---------------------------------------------------------------------------
 // Storage types.  bf16 and f16 are stored as raw 16-bit patterns; values are

@@ -4,13 +4,13 @@
 // Row r starts a new tile when
 //   - r = 0 or r = split (the first star row, so cell rows and star rows
 //     never share a tile), or
-//   - off[r] / kTileEntries differs from off[r-1] / kTileEntries (a new
-//     window of entries begins), or
-//   - r / kTileRows differs from (r-1) / kTileRows (at most kTileRows rows), or
-//   - row r or row r-1 is long (more than kLongRow entries).
+//   - off[r] / entries differs from off[r-1] / entries (a new window of
+//     entries begins), or
+//   - r / rows differs from (r-1) / rows (at most `rows` rows per tile), or
+//   - row r or row r-1 is long (more than long_row entries).
 // A tile therefore holds either a single long row or rows that all start in
-// one window of kTileEntries entries, each at most kLongRow long: at most
-// kTileEntries + kLongRow - 1 entries.  The rule looks only at neighbouring
+// one window of `entries` entries, each at most long_row long: at most
+// entries + long_row - 1 entries.  The rule looks only at neighbouring
 // rows, so tiles are built in parallel (flag, scan, scatter) and are
 // deterministic.
 #include "common.h"
@@ -20,15 +20,16 @@ namespace gift {
 namespace {
 
 template <typename Off>
-__global__ void k_tile_flags(const Off *off, int64_t R, int64_t split, int32_t *flag) {
+__global__ void k_tile_flags(const Off *off, int64_t R, int64_t split, TileShape sh,
+                             int32_t *flag) {
   int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (r >= R) return;
   int f = 1;
   if (r > 0 && r != split) {
     const int64_t a = off[r - 1], b = off[r], c = off[r + 1];
-    const bool long_prev = b - a > kLongRow, long_cur = c - b > kLongRow;
-    f = (a / kTileEntries != b / kTileEntries) || ((r - 1) / kTileRows != r / kTileRows) ||
-        long_prev || long_cur;
+    const bool long_prev = b - a > sh.long_row, long_cur = c - b > sh.long_row;
+    f = (a / sh.entries != b / sh.entries) || ((r - 1) / sh.rows != r / sh.rows) || long_prev ||
+        long_cur;
   }
   flag[r] = f;
 }
@@ -46,14 +47,14 @@ __global__ void k_tile_scatter(const int32_t *flag, const int64_t *pos, int64_t 
 }
 
 template <typename Off>
-gift_status build_tiles_impl(const Off *off, int64_t R, int64_t split, hipStream_t st,
-                             int32_t *tile_row, int64_t *counts_dev) {
+gift_status build_tiles_impl(const Off *off, int64_t R, int64_t split, TileShape sh,
+                             hipStream_t st, int32_t *tile_row, int64_t *counts_dev) {
   Scratch sc(st);
   int32_t *flag = nullptr;
   int64_t *pos = nullptr;
   GIFT_TRY(sc.get(&flag, R, "tile flags"));
   GIFT_TRY(sc.get(&pos, R + 1, "tile positions"));
-  k_tile_flags<Off><<<grid_for(R), kBlock, 0, st>>>(off, R, split, flag);
+  k_tile_flags<Off><<<grid_for(R), kBlock, 0, st>>>(off, R, split, sh, flag);
   GIFT_TRY(check_launch("k_tile_flags"));
   GIFT_TRY(scan_i32_to_i64(flag, pos, R, st));
   k_tile_scatter<<<grid_for(R > 0 ? R : 1), kBlock, 0, st>>>(flag, pos, R, split, tile_row,
@@ -63,14 +64,9 @@ gift_status build_tiles_impl(const Off *off, int64_t R, int64_t split, hipStream
 
 }  // namespace
 
-gift_status build_tiles(const int32_t *off, int64_t R, int64_t split, hipStream_t st,
-                        int32_t *tile_row, int64_t *counts_dev) {
-  return build_tiles_impl<int32_t>(off, R, split, st, tile_row, counts_dev);
-}
-
-gift_status build_tiles64(const int64_t *off, int64_t R, int64_t split, hipStream_t st,
-                          int32_t *tile_row, int64_t *counts_dev) {
-  return build_tiles_impl<int64_t>(off, R, split, st, tile_row, counts_dev);
+gift_status build_tiles64(const int64_t *off, int64_t R, int64_t split, TileShape sh,
+                          hipStream_t st, int32_t *tile_row, int64_t *counts_dev) {
+  return build_tiles_impl<int64_t>(off, R, split, sh, st, tile_row, counts_dev);
 }
 
 }  // namespace gift
