@@ -234,8 +234,7 @@ gift_status gift_destroy_graph(gift_graph *g, void *stream) {
   dev_free(g->col, s);
   dev_free(g->w, s);
   dev_free(g->deg, s);
-  dev_free(g->tile_row, s);
-  dev_free(g->tile_ptr, s);
+  for (int c = 0; c < kTileClasses; ++c) dev_free(g->tiles[c], s);
   for (SigmaBlock &b : g->sig) {
     dev_free(b.val, s);
     dev_free(b.diag, s);

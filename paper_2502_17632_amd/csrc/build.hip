@@ -389,11 +389,7 @@ __global__ void k_row_ptr32(const int64_t *rp64, int64_t n, int32_t *rp32) {
   if (i <= n) rp32[i] = static_cast<int32_t>(rp64[i]);
 }
 
-__global__ void k_tile_ptr(const int32_t *tile_row, const int64_t *rp64, int64_t T,
-                           int32_t *tile_ptr) {
-  int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t <= T) tile_ptr[t] = static_cast<int32_t>(rp64[tile_row[t]]);
-}
+
 
 // ---------------------------------------------------------------------------
 // 6. merge into the CSR of A, degrees
@@ -548,20 +544,22 @@ __global__ void k_sigma_scale(const double *deg, int64_t R, double sigma, double
   diag[i] = static_cast<typename Store<D>::A>((sigma * si) * si);
 }
 
-// One block per SpMM row tile: a_ij = (w_ij s_i) s_j for the tile's entries.
+// One block per SpMM row tile (class 0): a_ij = (w_ij s_i) s_j for the tile's
+// entries.
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_sigma_values(const int32_t *row_ptr,
-                                                         const int32_t *tiles,
+                                                         const TileDesc *tiles,
                                                          const int32_t *col, const double *w,
                                                          const double *s,
                                                          typename Store<D>::T *val) {
-  __shared__ int32_t loff[kTileRows + 2];
-  __shared__ uint16_t seg[kTileCap + 1];
-  __shared__ double ls[kTileRows + 1];
-  const int64_t r0 = tiles[blockIdx.x], r1 = tiles[blockIdx.x + 1];
-  const int64_t p0 = row_ptr[r0], p1 = row_ptr[r1];
+  using TCL = TileClass<0>;
+  __shared__ int32_t loff[TCL::kRows + 2];
+  __shared__ uint16_t seg[TCL::kCap + 1];
+  __shared__ double ls[TCL::kRows + 1];
+  const TileDesc td = tiles[blockIdx.x];
+  const int64_t r0 = td.r0, r1 = td.r1, p0 = td.p0, p1 = td.p1;
   const int ns = static_cast<int>(r1 - r0);
-  if (ns == 1 && p1 - p0 > kLongRow) {
+  if (ns == 1 && p1 - p0 > TCL::kLong) {
     const double si = s[r0];
     for (int64_t p = p0 + threadIdx.x; p < p1; p += kBlock)
       val[p] = Store<D>::from_f64((w[p] * si) * s[col[p]]);
@@ -589,9 +587,9 @@ gift_status sigma_kernels(gift_graph *g, double sigma, SigmaBlock &b, hipStream_
   k_sigma_scale<D><<<grid_for(g->num_rows), kBlock, 0, st>>>(g->deg, g->num_rows, sigma, s,
                                                                static_cast<A *>(b.diag));
   GIFT_TRY(check_launch("k_sigma_scale"));
-  if (g->num_tiles > 0) {
-    k_sigma_values<D><<<static_cast<unsigned>(g->num_tiles), kBlock, 0, st>>>(
-        g->row_ptr, g->tile_row, g->col, g->w, s, static_cast<T *>(b.val));
+  if (g->num_tiles[0] > 0) {
+    k_sigma_values<D><<<static_cast<unsigned>(g->num_tiles[0]), kBlock, 0, st>>>(
+        g->row_ptr, g->tiles[0], g->col, g->w, s, static_cast<T *>(b.val));
     GIFT_TRY(check_launch("k_sigma_values"));
   }
   return GIFT_OK;
@@ -794,39 +792,45 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
     GIFT_TRY(check_launch("k_virtual_counts"));
   }
 
-  // 5. row_ptr and the SpMM row tiles
+  // 5. row_ptr and the SpMM row tiles of every class
   int64_t *rp64 = nullptr;
   GIFT_TRY(sc.get(&rp64, R + 1, "row offsets (64-bit)"));
   GIFT_TRY(scan_i32_to_i64(ucnt, rp64, R, st));
+  int32_t *tstart[kTileClasses];
   int64_t *tile_counts = nullptr;
-  GIFT_TRY(dev_alloc(reinterpret_cast<void **>(&g->tile_row), (R + 2) * 4, st, "row tiles"));
-  GIFT_TRY(sc.get(&tile_counts, 2, "tile counts"));
-  GIFT_TRY(build_tiles64(rp64, R, N, kSpmmTiles, st, g->tile_row, tile_counts));
-  int64_t h2[4] = {0, 0, 0, 0};
+  GIFT_TRY(sc.get(&tile_counts, 2 * kTileClasses, "tile counts"));
+  for (int c = 0; c < kTileClasses; ++c) {
+    GIFT_TRY(sc.get(&tstart[c], R + 2, "tile starts"));
+    GIFT_TRY(build_tiles64(rp64, R, N, kSpmmTiles[c], st, tstart[c], tile_counts + 2 * c));
+  }
+  int64_t h2[2 + 2 * kTileClasses] = {};
   {
-    const int64_t *ptrs[4] = {rp64 + R, rp64 + N, tile_counts, tile_counts + 1};
-    GIFT_TRY(read_scalars(sc, st, ptrs, 4, h2));
+    const int64_t *ptrs[2 + 2 * kTileClasses];
+    ptrs[0] = rp64 + R;
+    ptrs[1] = rp64 + N;
+    for (int i = 0; i < 2 * kTileClasses; ++i) ptrs[2 + i] = tile_counts + i;
+    GIFT_TRY(read_scalars(sc, st, ptrs, 2 + 2 * kTileClasses, h2));
   }
   const int64_t nnz = h2[0];
   if (nnz >= (int64_t(1) << 31))
     return set_error(GIFT_EUNSUPPORTED, "too many stored entries (%lld)", (long long)nnz);
   g->nnz = nnz;
   g->nnz_cells = h2[1];
-  g->num_tiles = h2[2];
-  g->num_tiles_cells = h2[3];
   GIFT_TRY(dev_alloc(reinterpret_cast<void **>(&g->row_ptr), (R + 1) * 4, st, "row_ptr"));
   GIFT_TRY(dev_alloc(reinterpret_cast<void **>(&g->col), nnz * 4, st, "col"));
   GIFT_TRY(dev_alloc(reinterpret_cast<void **>(&g->w), nnz * 8, st, "weights"));
   GIFT_TRY(dev_alloc(reinterpret_cast<void **>(&g->deg), R * 8, st, "degrees"));
-  g->bytes = (R + 1) * 4 + nnz * 12 + R * 8 + (R + 2) * 4;
+  g->bytes = (R + 1) * 4 + nnz * 12 + R * 8;
   k_row_ptr32<<<grid_for(R + 1), kBlock, 0, st>>>(rp64, R, g->row_ptr);
   GIFT_TRY(check_launch("k_row_ptr32"));
-  GIFT_TRY(dev_alloc(reinterpret_cast<void **>(&g->tile_ptr), (g->num_tiles + 1) * 4, st,
-                     "tile entry offsets"));
-  g->bytes += (g->num_tiles + 1) * 4;
-  k_tile_ptr<<<grid_for(g->num_tiles + 1), kBlock, 0, st>>>(g->tile_row, rp64, g->num_tiles,
-                                                             g->tile_ptr);
-  GIFT_TRY(check_launch("k_tile_ptr"));
+  for (int c = 0; c < kTileClasses; ++c) {
+    g->num_tiles[c] = h2[2 + 2 * c];
+    g->num_tiles_cells[c] = h2[3 + 2 * c];
+    GIFT_TRY(dev_alloc(reinterpret_cast<void **>(&g->tiles[c]),
+                       (g->num_tiles[c] + 1) * sizeof(TileDesc), st, "row tiles"));
+    g->bytes += (g->num_tiles[c] + 1) * static_cast<int64_t>(sizeof(TileDesc));
+    GIFT_TRY(tile_descs(tstart[c], rp64, g->num_tiles[c], st, g->tiles[c]));
+  }
 
   // 6. merge
   if (num_row_tiles > 0) {

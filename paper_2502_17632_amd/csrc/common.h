@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "gift.h"
@@ -84,6 +85,12 @@ struct Scratch {
 // ---------------------------------------------------------------------------
 // Resident graph.
 // ---------------------------------------------------------------------------
+// A row tile: rows [r0, r1), stored entries [p0, p1).
+struct TileDesc {
+  int32_t r0, r1, p0, p1;
+};
+constexpr int kTileClasses = 2;
+
 struct SigmaBlock {
   double sigma;
   void *val;  // storage type [nnz]: a_ij = (w_ij s_i) s_j
@@ -108,11 +115,13 @@ struct gift_graph {
   std::vector<gift::SigmaBlock> sig;
   int64_t bytes = 0;
   int device = 0;
-  // Row tiles of the SpMM: tile t covers rows [tile_row[t], tile_row[t+1]).
-  int32_t *tile_row = nullptr;  // int32[num_tiles + 1]
-  int32_t *tile_ptr = nullptr;  // int32[num_tiles + 1]: row_ptr[tile_row[t]]
-  int64_t num_tiles = 0;
-  int64_t num_tiles_cells = 0;  // tiles covering rows [0, N)
+  // Row tiles of the SpMM for every tile class (see tiles.hip): tiles[c][t]
+  // covers rows [r0, r1) and entries [p0, p1); the first num_tiles_cells[c]
+  // tiles cover the cell rows [0, N).
+  gift::TileDesc *tiles[gift::kTileClasses] = {};
+  int64_t num_tiles[gift::kTileClasses] = {};
+  int64_t num_tiles_cells[gift::kTileClasses] = {};
+  int32_t tile_class = 0;  // class used by gift_filter_placement
 };
 
 namespace gift {
@@ -141,12 +150,26 @@ gift_status scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, hipStrea
 struct TileShape {
   int32_t entries, rows, long_row;
 };
-// The SpMM's tiles.
-constexpr int kTileEntries = 2048;
-constexpr int kTileRows = 512;
-constexpr int kLongRow = 256;
-constexpr int kTileCap = kTileEntries + kLongRow - 1;  // entries of a multi-row tile
-constexpr TileShape kSpmmTiles{kTileEntries, kTileRows, kLongRow};
+// The SpMM's tile classes: class 0 stages up to 2303 entries of at most 512
+// rows per block, class 1 up to 1151 entries of at most 256 rows.
+template <int TC>
+struct TileClass;
+template <>
+struct TileClass<0> {
+  static constexpr int kEntries = 2048, kRows = 512, kLong = 256;
+  static constexpr int kCap = kEntries + kLong - 1;
+};
+template <>
+struct TileClass<1> {
+  static constexpr int kEntries = 1024, kRows = 256, kLong = 128;
+  static constexpr int kCap = kEntries + kLong - 1;
+};
+constexpr TileShape kSpmmTiles[kTileClasses] = {
+    {TileClass<0>::kEntries, TileClass<0>::kRows, TileClass<0>::kLong},
+    {TileClass<1>::kEntries, TileClass<1>::kRows, TileClass<1>::kLong}};
+// Tile descriptors from tile starts (tile_row[0..T]) and 64-bit row offsets.
+gift_status tile_descs(const int32_t *tile_row, const int64_t *rp64, int64_t T, hipStream_t st,
+                       TileDesc *out);
 // tile_row must hold R + 1 entries; counts_dev[0] = number of tiles T,
 // counts_dev[1] = tiles that start before row `split`.
 gift_status build_tiles64(const int64_t *off, int64_t R, int64_t split, TileShape sh,
@@ -226,6 +249,52 @@ struct Store<GIFT_F16> {
   static __device__ __forceinline__ T from_acc(A a) { return f32_to_f16(a); }
   static __device__ __forceinline__ T from_f64(double d) { return f32_to_f16(f64_to_f32_odd(d)); }
 };
+
+// Pointers into global memory.  Accesses through a pointer that was loaded
+// from a table compile to FLAT instructions unless its address space is
+// spelled out; to_global does that.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T *;
+template <typename T>
+__device__ __forceinline__ gptr<T> to_global(T *p) {
+  return (gptr<T>)p;
+}
+
+// Loads/stores p[i] of a trivially copyable struct through global
+// instructions, in the widest words its alignment allows (C++ cannot copy a
+// class object out of a qualified address space directly).
+template <typename T>
+struct GWord {
+  typedef uint32_t v4 __attribute__((ext_vector_type(4)));
+  typedef uint32_t v2 __attribute__((ext_vector_type(2)));
+  using type = std::conditional_t<
+      alignof(T) >= 16 && sizeof(T) % 16 == 0, v4,
+      std::conditional_t<alignof(T) >= 8 && sizeof(T) % 8 == 0, v2,
+                         std::conditional_t<alignof(T) >= 4 && sizeof(T) % 4 == 0, uint32_t,
+                                            uint16_t>>>;
+  static constexpr int kWords = sizeof(T) / sizeof(type);
+  static_assert(sizeof(T) % sizeof(type) == 0, "struct size must be a multiple of 2 bytes");
+};
+template <typename T>
+__device__ __forceinline__ T gload(const T *p, int64_t i) {
+  using W = typename GWord<T>::type;
+  const gptr<const W> q = to_global(reinterpret_cast<const W *>(p + i));
+  W w[GWord<T>::kWords];
+#pragma unroll
+  for (int k = 0; k < GWord<T>::kWords; ++k) w[k] = q[k];
+  T t;
+  __builtin_memcpy(&t, w, sizeof(T));
+  return t;
+}
+template <typename T>
+__device__ __forceinline__ void gstore(T *p, int64_t i, const T &t) {
+  using W = typename GWord<T>::type;
+  const gptr<W> q = to_global(reinterpret_cast<W *>(p + i));
+  W w[GWord<T>::kWords];
+  __builtin_memcpy(w, &t, sizeof(T));
+#pragma unroll
+  for (int k = 0; k < GWord<T>::kWords; ++k) q[k] = w[k];
+}
 
 // Blocks are dispatched round-robin over the 8 XCDs.  Remap so that every XCD
 // works on one contiguous range of logical blocks (and so of rows): the signal

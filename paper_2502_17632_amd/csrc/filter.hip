@@ -9,45 +9,27 @@
 // term order, and writes the caller's output; iterates needed by earlier terms
 // are kept in their own buffers.
 //
-// The pass is bound by HBM bandwidth (about 0.4 flop per byte): it streams
-// row_ptr, col and the values once and gathers signal rows.  A group of G
-// lanes works on one row (G per row segment: cell rows are short, star rows
-// long), the lanes of a group read consecutive entries, and the group's
-// partial sums are combined with cross-lane shuffles.  Blocks are remapped so
-// each XCD works on one contiguous range of rows.
+// The pass is bound by memory traffic (about 0.4 flop per algorithmic byte):
+// it streams each tile's col/values once and gathers signal rows.  One block
+// per row tile: all of a thread's loads are issued at once (col/values, the
+// rows' offsets and diagonal, then the gathers), products are staged in LDS
+// and each row is summed by a group of lanes sized to the tile.  Blocks are
+// remapped so each XCD works on one contiguous range of tiles.
+//
+// The same launch sequence serves one graph and a batch of graphs: in a batch
+// every tile names its graph, whose CSR, values, I/O and row offset in the
+// shared signal buffers come from a small device table.
 #include <cmath>
 #include <cstring>
+#include <optional>
 
 #include "common.h"
 #include "devutil.h"
+#include "filter.h"
 
 namespace gift {
 
-constexpr int kMaxTerms = 64;
-
-struct PassArgs {
-  const int32_t *row_ptr;
-  const int32_t *col;
-  const void *val;
-  const void *diag;
-  const void *x;
-  void *y;
-  const int32_t *tile_row;  // tiles [0, num_tiles) of this launch
-  const int32_t *tile_ptr;  // first entry of every tile
-};
-
-struct FinalArgs {
-  int32_t num_terms;
-  int32_t in_dtype, out_dtype;
-  int32_t col0;  // first column of this chunk in the caller's matrices
-  const void *src[kMaxTerms];  // saved iterate of each term; NULL = this pass
-  double alpha[kMaxTerms];
-  const void *x_in;
-  int64_t ld_in;
-  void *y_out;
-  int64_t ld_out;
-  const uint8_t *fixed;
-};
+namespace {
 
 template <typename T, int C>
 struct SigRow {
@@ -59,19 +41,43 @@ struct SigRow {
 };
 
 template <typename T, int C>
-__device__ __forceinline__ typename SigRow<T, C>::V load_row(const T *__restrict__ x, int64_t r) {
-  return reinterpret_cast<const typename SigRow<T, C>::V *>(x)[r];
+__device__ __forceinline__ typename SigRow<T, C>::V load_row(const T *x, int64_t r) {
+  return gload(reinterpret_cast<const typename SigRow<T, C>::V *>(x), r);
 }
 
 __device__ __forceinline__ double load_in(const void *p, int32_t dt, int64_t i) {
-  return dt == GIFT_F64 ? static_cast<const double *>(p)[i]
-                        : static_cast<double>(static_cast<const float *>(p)[i]);
+  return dt == GIFT_F64 ? to_global(static_cast<const double *>(p))[i]
+                        : static_cast<double>(to_global(static_cast<const float *>(p))[i]);
 }
 
-// Writes row `row` of the pass result: the stored iterate, or (last pass) the
-// float64 combine of all terms in term order.
+// Tiles and graphs of one launch: a single graph (`one`, kBatch false) or a
+// batch (`graphs` indexed by `tile_graph`, kBatch true).
+struct LaunchArgs {
+  const TileDesc *tiles;
+  const int32_t *tile_graph;
+  const GraphDev *graphs;
+  GraphDev one;
+};
+
+template <bool kBatch>
+__device__ __forceinline__ GraphDev graph_of(const LaunchArgs &l, uint32_t tile) {
+  if constexpr (kBatch) return gload(l.graphs, to_global(l.tile_graph)[tile]);
+  else return l.one;
+}
+
+struct FinalArgs {
+  int32_t num_terms;
+  int32_t in_dtype, out_dtype;
+  int32_t col0;  // first column of this chunk in the caller's matrices
+  const void *src[kMaxTerms];  // saved iterate of each term; NULL = this pass
+  double alpha[kMaxTerms];
+};
+
+// Writes local row `lr` of the pass result: the stored iterate, or (last
+// pass) the float64 combine of all terms in term order.
 template <int D, int C, bool kFinal>
-__device__ __forceinline__ void emit_row(const PassArgs &p, const FinalArgs &f, int64_t row,
+__device__ __forceinline__ void emit_row(const FinalArgs &f, const GraphDev &gd,
+                                         typename Store<D>::T *y, int64_t lr,
                                          const typename Store<D>::A *acc) {
   using S = Store<D>;
   using T = typename S::T;
@@ -79,25 +85,27 @@ __device__ __forceinline__ void emit_row(const PassArgs &p, const FinalArgs &f, 
     typename SigRow<T, C>::V out;
 #pragma unroll
     for (int c = 0; c < C; ++c) out.v[c] = S::from_acc(acc[c]);
-    reinterpret_cast<typename SigRow<T, C>::V *>(p.y)[row] = out;
+    gstore(reinterpret_cast<typename SigRow<T, C>::V *>(y), lr, out);
   } else {
-    const bool fixed = f.fixed && f.fixed[row];
+    const GraphIO &io = gd.io;
+    const bool fixed = io.fixed && to_global(io.fixed)[lr];
+    const int64_t srow = gd.row_off + lr;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       double s = 0.0;
       if (fixed) {
-        s = load_in(f.x_in, f.in_dtype, row * f.ld_in + f.col0 + c);
+        s = load_in(io.x_in, f.in_dtype, lr * io.ld_in + f.col0 + c);
       } else {
         for (int t = 0; t < f.num_terms; ++t) {
           const T *src = static_cast<const T *>(f.src[t]);
-          double v = src ? static_cast<double>(S::load(src[row * C + c]))
+          double v = src ? static_cast<double>(S::load(to_global(src)[srow * C + c]))
                          : static_cast<double>(acc[c]);
           s = s + f.alpha[t] * v;
         }
       }
-      const int64_t o = row * f.ld_out + f.col0 + c;
-      if (f.out_dtype == GIFT_F64) static_cast<double *>(f.y_out)[o] = s;
-      else static_cast<float *>(f.y_out)[o] = static_cast<float>(s);
+      const int64_t o = lr * io.ld_out + f.col0 + c;
+      if (f.out_dtype == GIFT_F64) to_global(static_cast<double *>(io.y_out))[o] = s;
+      else to_global(static_cast<float *>(io.y_out))[o] = static_cast<float>(s);
     }
   }
 }
@@ -111,44 +119,50 @@ __device__ __forceinline__ int lanes_for(int rows) {
 
 // One SpMM pass over the tiles of this launch, one tile per block.
 //
-// Multi-row tile: all entries are fetched at once (coalesced col/value loads,
-// then the signal gathers, up to kStage per thread in flight), their products
-// staged in LDS, then each row is summed by a group of lanes sized to the
-// tile's row count.  When the products would not fit the LDS budget (wide
-// signal rows) the entries (col, value) are staged instead and the row groups
-// gather the signal themselves.  Single long row: the whole block strides
-// over the row and reduces across its waves.
-template <int D, int C, bool kFinal>
-__global__ __launch_bounds__(kBlock) void k_spmm(PassArgs p, FinalArgs f) {
+// Multi-row tile: every load is issued up front (inactive slots read entry 0
+// or row 0 of the tile's graph, always valid) so a thread has all its
+// col/value, offset and diagonal loads in flight at once, then all its
+// gathers; the products are staged in LDS and each row is summed by a group
+// of lanes sized to the tile's row count.  When the products would not fit
+// the LDS budget (wide signal rows) the entries (col, value) are staged
+// instead and the row groups gather the signal themselves.  Single long row:
+// the whole block strides over the row and reduces across its waves.
+template <int D, int C, bool kFinal, int TC, bool kBatch>
+__global__ __launch_bounds__(kBlock) void k_spmm(LaunchArgs l, const void *xin, void *yout,
+                                                 FinalArgs f) {
   using S = Store<D>;
   using T = typename S::T;
   using A = typename S::A;
+  using TCL = TileClass<TC>;
   constexpr bool kStageProducts = C * sizeof(A) <= 8;
-  constexpr int kStage = (kTileCap + kBlock - 1) / kBlock;
-  __shared__ int32_t loff[kTileRows + 1];
-  __shared__ A ldx[kStageProducts ? kTileRows * C : 1];
-  __shared__ A lprod[kStageProducts ? kTileCap * C : 1];
-  __shared__ int32_t lcol[kStageProducts ? 1 : kTileCap];
-  __shared__ A lval[kStageProducts ? 1 : kTileCap];
+  constexpr int kStage = (TCL::kCap + kBlock - 1) / kBlock;
+  __shared__ int32_t loff[TCL::kRows + 1];
+  __shared__ A ldx[kStageProducts ? TCL::kRows * C : 1];
+  __shared__ A lprod[kStageProducts ? TCL::kCap * C : 1];
+  __shared__ int32_t lcol[kStageProducts ? 1 : TCL::kCap];
+  __shared__ A lval[kStageProducts ? 1 : TCL::kCap];
   __shared__ A lred[kBlock / kWave][C];
 
   const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x);
   const int tid = threadIdx.x;
-  const int64_t r0 = p.tile_row[tile], r1 = p.tile_row[tile + 1];
-  const int64_t p0 = p.tile_ptr[tile], p1 = p.tile_ptr[tile + 1];
-  const int nrows = static_cast<int>(r1 - r0);
-  const int64_t n = p1 - p0;
-  const T *__restrict__ x = static_cast<const T *>(p.x);
-  const T *__restrict__ val = static_cast<const T *>(p.val);
-  const int32_t *__restrict__ col = p.col;
-  const A *__restrict__ diag = static_cast<const A *>(p.diag);
+  const TileDesc td = gload(l.tiles, tile);
+  const GraphDev gd = graph_of<kBatch>(l, tile);
+  const int32_t r0 = td.r0, r1 = td.r1, p0 = td.p0, p1 = td.p1;
+  const int nrows = r1 - r0;
+  const int n = p1 - p0;
+  const T *x = static_cast<const T *>(xin) + gd.row_off * C;
+  T *y = kFinal ? nullptr : static_cast<T *>(yout) + gd.row_off * C;
+  const gptr<const T> val = to_global(static_cast<const T *>(gd.val));
+  const gptr<const int32_t> col = to_global(gd.col);
+  const gptr<const int32_t> row_ptr = to_global(gd.row_ptr);
+  const gptr<const A> diag = to_global(static_cast<const A *>(gd.diag));
 
-  if (nrows == 1 && n > kLongRow) {
+  if (nrows == 1 && n > TCL::kLong) {
     // single long row
     A acc[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = 0;
-    int64_t q = p0 + tid;
+    int q = p0 + tid;
     for (; q + 3 * kBlock < p1; q += 4 * kBlock) {
       int32_t j[4];
       A v[4];
@@ -157,12 +171,13 @@ __global__ __launch_bounds__(kBlock) void k_spmm(PassArgs p, FinalArgs f) {
         j[u] = col[q + u * kBlock];
         v[u] = S::load(val[q + u * kBlock]);
       }
+      typename SigRow<T, C>::V xr[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const auto xr = load_row<T, C>(x, j[u]);
+      for (int u = 0; u < 4; ++u) xr[u] = load_row<T, C>(x, j[u]);
 #pragma unroll
-        for (int c = 0; c < C; ++c) acc[c] += v[u] * S::load(xr.v[c]);
-      }
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[c] += v[u] * S::load(xr[u].v[c]);
     }
     for (; q < p1; q += kBlock) {
       const auto xr = load_row<T, C>(x, col[q]);
@@ -186,46 +201,40 @@ __global__ __launch_bounds__(kBlock) void k_spmm(PassArgs p, FinalArgs f) {
         for (int w = 1; w < kBlock / kWave; ++w) s += lred[w][c];
         tot[c] = s + dg * S::load(xi.v[c]);
       }
-      emit_row<D, C, kFinal>(p, f, r0, tot);
+      emit_row<D, C, kFinal>(f, gd, y, r0, tot);
     }
     return;
   }
 
-  // ---- multi-row tile (n <= kTileCap)
-  // Every load is issued unconditionally (inactive slots read entry p0 or
-  // row 0, always valid) so that all of a thread's loads are in flight at
-  // once: first col/value and the rows' offsets and diagonal terms, then the
-  // signal gathers; only then are results written to LDS.
+  // ---- multi-row tile (n <= kCap)
   {
     int32_t jj[kStage];
     A vv[kStage];
 #pragma unroll
     for (int k = 0; k < kStage; ++k) {
       const int i = tid + k * kBlock;
-      const int64_t q = i < n ? p0 + i : 0;
+      const int q = i < n ? p0 + i : 0;
       jj[k] = col[q];
       vv[k] = S::load(val[q]);
     }
-    constexpr int kRowIters = (kTileRows + 1 + kBlock - 1) / kBlock;
+    constexpr int kRowIters = (TCL::kRows + 1 + kBlock - 1) / kBlock;
     int32_t ro[kRowIters];
 #pragma unroll
     for (int k = 0; k < kRowIters; ++k) {
       const int i = tid + k * kBlock;
-      ro[k] = p.row_ptr[i <= nrows ? r0 + i : r0];
+      ro[k] = row_ptr[i <= nrows ? r0 + i : r0];
     }
-    constexpr int kDiagIters = kTileRows / kBlock;
-    A dg[kDiagIters];
-    typename SigRow<T, C>::V xr_row[kDiagIters];
+    constexpr int kDiagIters = (TCL::kRows + kBlock - 1) / kBlock;
     if constexpr (kStageProducts) {
+      A dg[kDiagIters];
+      typename SigRow<T, C>::V xr_row[kDiagIters];
 #pragma unroll
       for (int k = 0; k < kDiagIters; ++k) {
         const int i = tid + k * kBlock;
-        const int64_t r = i < nrows ? r0 + i : r0;
+        const int r = i < nrows ? r0 + i : r0;
         dg[k] = diag[r];
         xr_row[k] = load_row<T, C>(x, r);
       }
-    }
-    if constexpr (kStageProducts) {
       typename SigRow<T, C>::V xv[kStage];
 #pragma unroll
       for (int k = 0; k < kStage; ++k) xv[k] = load_row<T, C>(x, jj[k]);
@@ -258,7 +267,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm(PassArgs p, FinalArgs f) {
 #pragma unroll
     for (int k = 0; k < kRowIters; ++k) {
       const int i = tid + k * kBlock;
-      if (i <= nrows) loff[i] = static_cast<int32_t>(ro[k] - p0);
+      if (i <= nrows) loff[i] = ro[k] - p0;
     }
   }
   __syncthreads();
@@ -312,34 +321,34 @@ __global__ __launch_bounds__(kBlock) void k_spmm(PassArgs p, FinalArgs f) {
 #pragma unroll
         for (int c = 0; c < C; ++c) acc[c] = acc[c] + dg * S::load(xi.v[c]);
       }
-      emit_row<D, C, kFinal>(p, f, r0 + rr, acc);
+      emit_row<D, C, kFinal>(f, gd, y, r0 + rr, acc);
     }
   }
 }
 
-// Rows [0, N): the caller's signal, rounded to the storage type.
-template <int D, int C>
-__global__ void k_prep_cells(const void *x_in, int64_t ld_in, int32_t in_dtype, int32_t col0,
-                             int64_t N, typename Store<D>::T *x0) {
-  int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= N * C) return;
-  int64_t r = i / C;
-  int c = static_cast<int>(i - r * C);
-  x0[i] = Store<D>::from_f64(load_in(x_in, in_dtype, r * ld_in + col0 + c));
-}
-
-// Star rows [N, R): the mean of the net's cells (float64 sum), one wave each.
-template <int D, int C>
-__global__ __launch_bounds__(kBlock) void k_prep_stars(const int32_t *row_ptr,
-                                                       const int32_t *col, const void *x_in,
-                                                       int64_t ld_in, int32_t in_dtype,
-                                                       int32_t col0, int64_t N, int64_t V,
-                                                       typename Store<D>::T *x0) {
+// x0 for the rows of one tile: cell rows are the caller's signal rounded to
+// the storage type, star rows the float64 mean of their net's cells (one
+// wave per star row).  A tile never mixes cell rows and star rows.
+template <int D, int C, bool kBatch>
+__global__ __launch_bounds__(kBlock) void k_prep(LaunchArgs l, int32_t in_dtype, int32_t col0,
+                                                 void *x0v) {
+  const TileDesc td = gload(l.tiles, blockIdx.x);
+  const GraphDev gd = graph_of<kBatch>(l, blockIdx.x);
+  const GraphIO &io = gd.io;
+  const gptr<typename Store<D>::T> x0 =
+      to_global(static_cast<typename Store<D>::T *>(x0v)) + gd.row_off * C;
+  const gptr<const int32_t> row_ptr = to_global(gd.row_ptr), col = to_global(gd.col);
+  if (td.r0 < io.num_cells) {
+    const int n = (td.r1 - td.r0) * C;
+    for (int i = threadIdx.x; i < n; i += kBlock) {
+      const int64_t r = td.r0 + i / C;
+      const int c = i % C;
+      x0[r * C + c] = Store<D>::from_f64(load_in(io.x_in, in_dtype, r * io.ld_in + col0 + c));
+    }
+    return;
+  }
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t waves = static_cast<int64_t>(gridDim.x) * (kBlock / kWave);
-  for (int64_t v = static_cast<int64_t>(blockIdx.x) * (kBlock / kWave) + threadIdx.x / kWave;
-       v < V; v += waves) {
-    const int64_t r = N + v;
+  for (int r = td.r0 + static_cast<int>(threadIdx.x) / kWave; r < td.r1; r += kBlock / kWave) {
     const int32_t p0 = row_ptr[r], p1 = row_ptr[r + 1];
     double s[C];
 #pragma unroll
@@ -347,7 +356,7 @@ __global__ __launch_bounds__(kBlock) void k_prep_stars(const int32_t *row_ptr,
     for (int32_t q = p0 + lane; q < p1; q += kWave) {
       const int64_t j = col[q];
 #pragma unroll
-      for (int c = 0; c < C; ++c) s[c] += load_in(x_in, in_dtype, j * ld_in + col0 + c);
+      for (int c = 0; c < C; ++c) s[c] += load_in(io.x_in, in_dtype, j * io.ld_in + col0 + c);
     }
 #pragma unroll
     for (int c = 0; c < C; ++c)
@@ -355,139 +364,136 @@ __global__ __launch_bounds__(kBlock) void k_prep_stars(const int32_t *row_ptr,
     if (lane == 0) {
       const double m = static_cast<double>(p1 - p0);
 #pragma unroll
-      for (int c = 0; c < C; ++c) x0[r * C + c] = Store<D>::from_f64(m > 0 ? s[c] / m : 0.0);
+      for (int c = 0; c < C; ++c)
+        x0[static_cast<int64_t>(r) * C + c] = Store<D>::from_f64(m > 0 ? s[c] / m : 0.0);
     }
   }
 }
-
-namespace {
-
-struct Group {
-  double sigma;
-  int32_t kmax;
-  const SigmaBlock *blk;
-};
 
 // Algorithmic bytes of one SpMM pass: row_ptr, col and values of the rows it
 // covers, their diagonal, every signal row read once, the iterate written.
 // The last pass covers the cell rows only, reads the saved iterates of the
 // other terms and writes the output instead.
-template <int D, int C>
-double pass_bytes(const gift_graph *g, bool fin, int32_t nt, int32_t out_dt) {
-  const double bt = sizeof(typename Store<D>::T), ba = sizeof(typename Store<D>::A);
-  const double rows = static_cast<double>(fin ? g->num_cells : g->num_rows);
-  const double nnz = static_cast<double>(fin ? g->nnz_cells : g->nnz);
-  const double R = static_cast<double>(g->num_rows);
-  double b = 4.0 * (rows + 1) + (4.0 + bt) * nnz + ba * rows + bt * C * R;
+double pass_bytes(const FilterPlan &pl, int C, bool fin) {
+  const double bt = static_cast<double>(dtype_size(pl.storage));
+  const double ba = static_cast<double>(accum_size(pl.storage));
+  const double rows = static_cast<double>(fin ? pl.cell_rows : pl.R);
+  const double nnz = static_cast<double>(fin ? pl.nnz_cells : pl.nnz);
+  const double R = static_cast<double>(pl.R);
+  const double b = 4.0 * (rows + 1) + (4.0 + bt) * nnz + ba * rows + bt * C * R;
   if (!fin) return b + bt * C * rows;
-  return b + (nt - 1) * bt * C * rows + (out_dt == GIFT_F64 ? 8.0 : 4.0) * C * rows;
+  return b + (pl.num_terms - 1) * bt * C * rows +
+         (pl.out_dtype == GIFT_F64 ? 8.0 : 4.0) * C * rows;
 }
 
-template <int D, int C>
-gift_status run_chunk(const gift_graph *g, const std::vector<Group> &groups,
-                      const gift_term *terms, int32_t nt, const void *x_in, int64_t ld_in,
-                      int32_t in_dt, void *y_out, int64_t ld_out, int32_t out_dt,
-                      const uint8_t *fixed, int32_t col0, hipStream_t st) {
+LaunchArgs launch_args(const FilterPlan &pl, const PlanGroup &grp, bool fin) {
+  LaunchArgs l{};
+  l.tiles = fin ? pl.final_tiles : pl.tiles;
+  l.tile_graph = fin ? pl.final_tile_graph : pl.tile_graph;
+  l.graphs = grp.graphs;
+  l.one = pl.one;
+  l.one.val = grp.val;
+  l.one.diag = grp.diag;
+  return l;
+}
+
+template <int D, int C, int TC, bool kBatch>
+gift_status enqueue_chunk(const FilterPlan &pl, const ChunkBuffers &bf, int32_t col0,
+                          hipStream_t st) {
   using T = typename Store<D>::T;
-  const int64_t N = g->num_cells, V = g->num_virtual, R = g->num_rows;
-  Scratch sc(st);
-  T *x0 = nullptr, *ping = nullptr, *pong = nullptr;
-  GIFT_TRY(sc.get(&x0, R * C, "signal x0"));
-  GIFT_TRY(sc.get(&ping, R * C, "signal ping"));
-  GIFT_TRY(sc.get(&pong, R * C, "signal pong"));
-  // saved iterate for every term that is not the very last pass
-  std::vector<T *> saved(nt, nullptr);
-  const Group &last = groups.back();
-  for (int32_t t = 0; t < nt; ++t) {
-    bool is_final = terms[t].sigma == last.sigma && terms[t].order == last.kmax;
-    if (is_final) continue;
-    for (int32_t u = 0; u < t; ++u)
-      if (terms[u].sigma == terms[t].sigma && terms[u].order == terms[t].order) saved[t] = saved[u];
-    if (!saved[t]) GIFT_TRY(sc.get(&saved[t], R * C, "saved iterate"));
+  T *x0 = static_cast<T *>(bf.x0), *ping = static_cast<T *>(bf.ping),
+    *pong = static_cast<T *>(bf.pong);
+  if (pl.num_tiles > 0) {
+    k_prep<D, C, kBatch><<<static_cast<unsigned>(pl.num_tiles), kBlock, 0, st>>>(
+        launch_args(pl, pl.groups.front(), false), pl.in_dtype, col0, x0);
+    GIFT_TRY(check_launch("k_prep"));
   }
-
-  k_prep_cells<D, C><<<grid_for(N * C), kBlock, 0, st>>>(x_in, ld_in, in_dt, col0, N, x0);
-  GIFT_TRY(check_launch("k_prep_cells"));
-  if (V > 0) {
-    k_prep_stars<D, C><<<grid_for(V * kWave), kBlock, 0, st>>>(g->row_ptr, g->col, x_in, ld_in,
-                                                                in_dt, col0, N, V, x0);
-    GIFT_TRY(check_launch("k_prep_stars"));
-  }
-
   FinalArgs fa{};
-  fa.num_terms = nt;
-  fa.in_dtype = in_dt;
-  fa.out_dtype = out_dt;
+  fa.num_terms = pl.num_terms;
+  fa.in_dtype = pl.in_dtype;
+  fa.out_dtype = pl.out_dtype;
   fa.col0 = col0;
-  fa.x_in = x_in;
-  fa.ld_in = ld_in;
-  fa.y_out = y_out;
-  fa.ld_out = ld_out;
-  fa.fixed = fixed;
-  for (int32_t t = 0; t < nt; ++t) {
-    fa.src[t] = saved[t];
-    fa.alpha[t] = terms[t].alpha;
+  for (int32_t t = 0; t < pl.num_terms; ++t) {
+    fa.src[t] = bf.saved[t];
+    fa.alpha[t] = pl.terms[t].alpha;
   }
-
-  for (size_t gi = 0; gi < groups.size(); ++gi) {
-    const Group &grp = groups[gi];
+  const size_t ng = pl.groups.size();
+  for (size_t gi = 0; gi < ng; ++gi) {
+    const PlanGroup &grp = pl.groups[gi];
     const T *cur = x0;
     for (int32_t k = 1; k <= grp.kmax; ++k) {
-      const bool fin = gi + 1 == groups.size() && k == grp.kmax;
+      const bool fin = gi + 1 == ng && k == grp.kmax;
       T *dst = nullptr;
       if (!fin) {
-        for (int32_t t = 0; t < nt; ++t)
-          if (terms[t].sigma == grp.sigma && terms[t].order == k) dst = saved[t];
+        for (int32_t t = 0; t < pl.num_terms; ++t)
+          if (pl.terms[t].sigma == grp.sigma && pl.terms[t].order == k)
+            dst = static_cast<T *>(bf.saved[t]);
         if (!dst) dst = (cur == ping) ? pong : ping;
       }
-      PassArgs pa{};
-      pa.row_ptr = g->row_ptr;
-      pa.col = g->col;
-      pa.val = grp.blk->val;
-      pa.diag = grp.blk->diag;
-      pa.x = cur;
-      pa.y = dst;
-      pa.tile_row = g->tile_row;
-      pa.tile_ptr = g->tile_ptr;
-      const int64_t tiles = fin ? g->num_tiles_cells : g->num_tiles;
-      if (tiles == 0) continue;
-      const unsigned grid = static_cast<unsigned>(tiles);
-      {
-        ProfScope ps(st, fin ? GIFT_PROF_SPMM_FINAL : GIFT_PROF_SPMM,
-                     pass_bytes<D, C>(g, fin, nt, out_dt));
-        if (fin) k_spmm<D, C, true><<<grid, kBlock, 0, st>>>(pa, fa);
-        else k_spmm<D, C, false><<<grid, kBlock, 0, st>>>(pa, fa);
+      const int64_t tiles = fin ? pl.num_final_tiles : pl.num_tiles;
+      if (tiles > 0) {
+        std::optional<ProfScope> ps;
+        if (pl.profile)
+          ps.emplace(st, fin ? GIFT_PROF_SPMM_FINAL : GIFT_PROF_SPMM, pass_bytes(pl, C, fin));
+        const LaunchArgs l = launch_args(pl, grp, fin);
+        const unsigned grid = static_cast<unsigned>(tiles);
+        if (fin) k_spmm<D, C, true, TC, kBatch><<<grid, kBlock, 0, st>>>(l, cur, nullptr, fa);
+        else k_spmm<D, C, false, TC, kBatch><<<grid, kBlock, 0, st>>>(l, cur, dst, fa);
+        GIFT_TRY(check_launch("k_spmm"));
       }
-      GIFT_TRY(check_launch("k_spmm"));
-      cur = dst;
+      if (!fin) cur = dst;
     }
   }
   return GIFT_OK;
 }
 
+template <int D, int C>
+gift_status enqueue_chunk_tc(const FilterPlan &pl, const ChunkBuffers &bf, int32_t col0,
+                             hipStream_t st) {
+  const bool batch = pl.groups.front().graphs != nullptr;
+  if (pl.tile_class == 1)
+    return batch ? enqueue_chunk<D, C, 1, true>(pl, bf, col0, st)
+                 : enqueue_chunk<D, C, 1, false>(pl, bf, col0, st);
+  return batch ? enqueue_chunk<D, C, 0, true>(pl, bf, col0, st)
+               : enqueue_chunk<D, C, 0, false>(pl, bf, col0, st);
+}
+
 template <int D>
-gift_status run_chunk_c(int C, const gift_graph *g, const std::vector<Group> &groups,
-                        const gift_term *terms, int32_t nt, const void *x_in, int64_t ld_in,
-                        int32_t in_dt, void *y_out, int64_t ld_out, int32_t out_dt,
-                        const uint8_t *fixed, int32_t col0, hipStream_t st) {
+gift_status enqueue_chunk_c(const FilterPlan &pl, const ChunkBuffers &bf, int C, int32_t col0,
+                            hipStream_t st) {
   switch (C) {
-    case 1: return run_chunk<D, 1>(g, groups, terms, nt, x_in, ld_in, in_dt, y_out, ld_out, out_dt, fixed, col0, st);
-    case 2: return run_chunk<D, 2>(g, groups, terms, nt, x_in, ld_in, in_dt, y_out, ld_out, out_dt, fixed, col0, st);
-    case 4: return run_chunk<D, 4>(g, groups, terms, nt, x_in, ld_in, in_dt, y_out, ld_out, out_dt, fixed, col0, st);
-    case 8: return run_chunk<D, 8>(g, groups, terms, nt, x_in, ld_in, in_dt, y_out, ld_out, out_dt, fixed, col0, st);
-    case 16: return run_chunk<D, 16>(g, groups, terms, nt, x_in, ld_in, in_dt, y_out, ld_out, out_dt, fixed, col0, st);
+    case 1: return enqueue_chunk_tc<D, 1>(pl, bf, col0, st);
+    case 2: return enqueue_chunk_tc<D, 2>(pl, bf, col0, st);
+    case 4: return enqueue_chunk_tc<D, 4>(pl, bf, col0, st);
+    case 8: return enqueue_chunk_tc<D, 8>(pl, bf, col0, st);
+    case 16: return enqueue_chunk_tc<D, 16>(pl, bf, col0, st);
   }
   return set_error(GIFT_EUNSUPPORTED, "column chunk %d", C);
 }
 
+size_t round_up(size_t b) { return (b + 255) / 256 * 256; }
+
 }  // namespace
 
-// Terms grouped by distinct sigma (ascending), each with its highest order.
-gift_status plan_groups(const gift_graph *g, const gift_term *terms, int32_t nt,
-                        std::vector<Group> *out);
+int chunk_width(int remaining) {
+  return remaining >= 16 ? 16 : remaining >= 8 ? 8 : remaining >= 4 ? 4 : remaining >= 2 ? 2 : 1;
+}
+
+gift_status enqueue_filter_chunk(const FilterPlan &pl, const ChunkBuffers &bf, int C, int32_t col0,
+                                 hipStream_t st) {
+  if (pl.tile_class < 0 || pl.tile_class >= kTileClasses)
+    return set_error(GIFT_EINVAL, "tile class %d", pl.tile_class);
+  switch (pl.storage) {
+    case GIFT_F32: return enqueue_chunk_c<GIFT_F32>(pl, bf, C, col0, st);
+    case GIFT_F64: return enqueue_chunk_c<GIFT_F64>(pl, bf, C, col0, st);
+    case GIFT_BF16: return enqueue_chunk_c<GIFT_BF16>(pl, bf, C, col0, st);
+    case GIFT_F16: return enqueue_chunk_c<GIFT_F16>(pl, bf, C, col0, st);
+  }
+  return set_error(GIFT_EUNSUPPORTED, "storage %d", pl.storage);
+}
 
 gift_status plan_groups(const gift_graph *g, const gift_term *terms, int32_t nt,
-                        std::vector<Group> *out) {
+                        std::vector<PlanGroup> *out) {
   out->clear();
   for (int32_t t = 0; t < nt; ++t) {
     const gift_term &tm = terms[t];
@@ -501,17 +507,49 @@ gift_status plan_groups(const gift_graph *g, const gift_term *terms, int32_t nt,
       return set_error(GIFT_EINVAL, "term %d: sigma %g was not prepared for this graph", t,
                        tm.sigma);
     bool found = false;
-    for (Group &gr : *out)
+    for (PlanGroup &gr : *out)
       if (gr.sigma == tm.sigma) {
         if (tm.order > gr.kmax) gr.kmax = tm.order;
         found = true;
       }
-    if (!found) out->push_back(Group{tm.sigma, tm.order, b});
+    if (!found) out->push_back(PlanGroup{tm.sigma, tm.order, b->val, b->diag, nullptr});
   }
   for (size_t i = 1; i < out->size(); ++i)
     for (size_t j = i; j > 0 && (*out)[j].sigma < (*out)[j - 1].sigma; --j)
       std::swap((*out)[j], (*out)[j - 1]);
   return GIFT_OK;
+}
+
+// Buffers x0, ping, pong and one saved iterate per distinct (sigma, order)
+// term other than the one the last pass forms, each rounded to 256 bytes.
+size_t carve_chunk_buffers(const FilterPlan &pl, int C, unsigned char *base, ChunkBuffers *bf) {
+  const size_t rb = round_up(dtype_size(pl.storage) * C * static_cast<size_t>(pl.R));
+  const uintptr_t b = reinterpret_cast<uintptr_t>(base);
+  size_t off = 0;
+  auto slot = [&]() {
+    void *p = reinterpret_cast<void *>(b + off);
+    off += rb;
+    return p;
+  };
+  bf->x0 = slot();
+  bf->ping = slot();
+  bf->pong = slot();
+  const PlanGroup &last = pl.groups.back();
+  for (int32_t t = 0; t < pl.num_terms; ++t) {
+    bf->saved[t] = nullptr;
+    const gift_term &tm = pl.terms[t];
+    if (tm.sigma == last.sigma && tm.order == last.kmax) continue;
+    int32_t same = -1;
+    for (int32_t u = 0; u < t && same < 0; ++u)
+      if (pl.terms[u].sigma == tm.sigma && pl.terms[u].order == tm.order) same = u;
+    bf->saved[t] = same >= 0 ? bf->saved[same] : slot();
+  }
+  return off;
+}
+
+size_t chunk_buffer_bytes(const FilterPlan &pl, int C) {
+  ChunkBuffers bf;
+  return carve_chunk_buffers(pl, C, nullptr, &bf);
 }
 
 }  // namespace gift
@@ -533,23 +571,36 @@ extern "C" gift_status gift_filter_placement(const gift_graph *g, const gift_ter
     return set_error(GIFT_EUNSUPPORTED, "in_dtype must be F32 or F64");
   if (out_dt != GIFT_F32 && out_dt != GIFT_F64)
     return set_error(GIFT_EUNSUPPORTED, "out_dtype must be F32 or F64");
-  std::vector<gift::Group> groups;
-  GIFT_TRY(plan_groups(g, terms, nt, &groups));
+  FilterPlan pl;
+  GIFT_TRY(plan_groups(g, terms, nt, &pl.groups));
   if (g->num_cells == 0) return GIFT_OK;
   if (!x_in || !y_out) return set_error(GIFT_EINVAL, "x_in / y_out is NULL");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  int32_t col0 = 0;
-  while (col0 < num_cols) {
-    int rem = num_cols - col0;
-    int C = rem >= 16 ? 16 : rem >= 8 ? 8 : rem >= 4 ? 4 : rem >= 2 ? 2 : 1;
-    gift_status s = GIFT_OK;
-    switch (g->storage) {
-      case GIFT_F32: s = run_chunk_c<GIFT_F32>(C, g, groups, terms, nt, x_in, ld_in, in_dt, y_out, ld_out, out_dt, fixed, col0, st); break;
-      case GIFT_F64: s = run_chunk_c<GIFT_F64>(C, g, groups, terms, nt, x_in, ld_in, in_dt, y_out, ld_out, out_dt, fixed, col0, st); break;
-      case GIFT_BF16: s = run_chunk_c<GIFT_BF16>(C, g, groups, terms, nt, x_in, ld_in, in_dt, y_out, ld_out, out_dt, fixed, col0, st); break;
-      case GIFT_F16: s = run_chunk_c<GIFT_F16>(C, g, groups, terms, nt, x_in, ld_in, in_dt, y_out, ld_out, out_dt, fixed, col0, st); break;
-    }
-    if (s != GIFT_OK) return s;
+  const int tc = g->tile_class;
+  pl.storage = g->storage;
+  pl.tile_class = tc;
+  pl.R = g->num_rows;
+  pl.nnz = g->nnz;
+  pl.cell_rows = g->num_cells;
+  pl.nnz_cells = g->nnz_cells;
+  pl.tiles = g->tiles[tc];
+  pl.num_tiles = g->num_tiles[tc];
+  pl.final_tiles = g->tiles[tc];
+  pl.num_final_tiles = g->num_tiles_cells[tc];
+  pl.terms = terms;
+  pl.num_terms = nt;
+  pl.in_dtype = in_dt;
+  pl.out_dtype = out_dt;
+  pl.one = GraphDev{g->row_ptr, g->col, nullptr, nullptr, 0,
+                    GraphIO{x_in, ld_in, y_out, ld_out, fixed, g->num_cells}};
+  for (int32_t col0 = 0; col0 < num_cols;) {
+    const int C = chunk_width(num_cols - col0);
+    Scratch sc(st);
+    unsigned char *buf = nullptr;
+    GIFT_TRY(sc.get(&buf, chunk_buffer_bytes(pl, C), "filter signal buffers"));
+    ChunkBuffers bf;
+    carve_chunk_buffers(pl, C, buf, &bf);
+    GIFT_TRY(enqueue_filter_chunk(pl, bf, C, col0, st));
     col0 += C;
   }
   return GIFT_OK;

@@ -62,7 +62,22 @@ gift_status build_tiles_impl(const Off *off, int64_t R, int64_t split, TileShape
   return check_launch("k_tile_scatter");
 }
 
+__global__ void k_tile_descs(const int32_t *tile_row, const int64_t *rp64, int64_t T,
+                             TileDesc *out) {
+  int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  const int32_t a = tile_row[t], b = tile_row[t + 1];
+  out[t] = TileDesc{a, b, static_cast<int32_t>(rp64[a]), static_cast<int32_t>(rp64[b])};
+}
+
 }  // namespace
+
+gift_status tile_descs(const int32_t *tile_row, const int64_t *rp64, int64_t T, hipStream_t st,
+                       TileDesc *out) {
+  if (T <= 0) return GIFT_OK;
+  k_tile_descs<<<grid_for(T), kBlock, 0, st>>>(tile_row, rp64, T, out);
+  return check_launch("k_tile_descs");
+}
 
 gift_status build_tiles64(const int64_t *off, int64_t R, int64_t split, TileShape sh,
                           hipStream_t st, int32_t *tile_row, int64_t *counts_dev) {
