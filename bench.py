@@ -75,6 +75,102 @@ def filter_work(info, passes, cols):
     return full * (passes - 1) + (info["nnz_cells"] + info["num_cells"]) * cols
 
 
+def filter_bytes(nnz, rows, nnz_cells, cells, cols, passes, num_terms, storage):
+    """Algorithmic bytes of the whole filter: per pass row_ptr, col and values
+    of the rows it covers, their diagonal, every signal row read once and the
+    rows written; the last pass reads the saved iterates of the other terms
+    and writes the float32 output instead of an iterate."""
+    bt = {"f32": 4, "bf16": 2, "f16": 2, "f64": 8}[storage]
+    ba = 8 if storage == "f64" else 4
+
+    def one(r, z, fin):
+        b = 4 * (r + 1) + (4 + bt) * z + ba * r + bt * cols * rows
+        if not fin:
+            return b + bt * cols * r
+        return b + (num_terms - 1) * bt * cols * r + 4 * cols * r
+    return one(rows, nnz, False) * (passes - 1) + one(cells, nnz_cells, True)
+
+
+def bench_batched(gift, W, torch, storage, reps=10):
+    """64 designs (log-uniform 10k-300k movable cells, the medium generator,
+    per-design seeds), 8 columns each (4 placements), sigma 4, orders
+    1, 2, 4, 8, equal weights: the per-design path (64 filter calls) against
+    one tuned batch replaying its captured launch sequence."""
+    import numpy as np
+    orders = [1, 2, 4, 8]
+    terms = ([4.0] * 4, orders, [0.25] * 4)
+    sizes = W.batch_sizes(64)
+    log(f"[bench] batched {storage}: generating 64 designs")
+    nls = [W.sized(n, seed=1000 + i) for i, n in enumerate(sizes)]
+    xs = [torch.tensor(W.make_signal(nl, W.BATCH_NOISE, seed=1000 + i), dtype=torch.float32,
+                       device="cuda") for i, nl in enumerate(nls)]
+    graphs = [gift.build_graph(nl.num_cells, nl.net_ptr, nl.pin_cell, star_threshold=16,
+                               storage=storage, sigmas=[4.0]) for nl in nls]
+    infos = [g.info() for g in graphs]
+    nnz_cells = 0
+    for g, nl in zip(graphs, nls):
+        rp, _, _, _ = g.export()
+        nnz_cells += int(rp[nl.num_cells])
+    nnz = sum(i["nnz"] for i in infos)
+    rows = sum(i["num_rows"] for i in infos)
+    cells = sum(i["num_cells"] for i in infos)
+    work = ((nnz + rows) * (max(orders) - 1) + (nnz_cells + cells)) * 8
+    nbytes = filter_bytes(nnz, rows, nnz_cells, cells, 8, max(orders), len(orders), storage)
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3 / reps
+        return e0.elapsed_time(e1) / reps, wall
+
+    ys_alone = [torch.empty_like(x) for x in xs]
+
+    def alone():
+        for g, x, y in zip(graphs, xs, ys_alone):
+            gift.filter_placement(g, *terms, x, out=y)
+    ms_alone, wall_alone = timed(alone)
+
+    t0 = time.perf_counter()
+    b = gift.Batch(graphs, *terms, num_cols=8, tune=1)
+    create_s = time.perf_counter() - t0
+    ys = [torch.empty_like(x) for x in xs]
+    ms_batch, wall_batch = timed(lambda: b.run(xs, ys))
+    torch.cuda.synchronize()
+    worst = 0.0
+    for y, a in zip(ys, ys_alone):
+        den = a.abs().amax(dim=0).clamp_min(1e-30)
+        worst = max(worst, float(((y - a).abs().amax(dim=0) / den).max()))
+    info = b.info()
+    b.close()
+    for g in graphs:
+        g.close()
+    return {
+        "workload": "64 designs, log-uniform 10k-300k movable cells (medium generator, seeds "
+                    "1000+i), 8 columns, sigma 4, orders 1,2,4,8, equal weights",
+        "storage": storage, "cells": cells, "rows": rows, "nnz": nnz,
+        "per_design_ms": round(ms_alone, 4), "per_design_wall_ms": round(wall_alone, 4),
+        "batched_ms": round(ms_batch, 4), "batched_wall_ms": round(wall_batch, 4),
+        "speedup": round(ms_alone / ms_batch, 3),
+        "batched_nnz_cols_per_s": work / (ms_batch * 1e-3),
+        "per_design_nnz_cols_per_s": work / (ms_alone * 1e-3),
+        "batched_algorithmic_GBs": round(nbytes / (ms_batch * 1e-3) / 1e9, 1),
+        "max_normwise_diff_vs_per_design": worst,
+        "schedule": {"tile_class": info["tile_class"], "chunk_cols": info["chunk_cols"],
+                     "tuned": info["tuned"], "tune_s": round(create_s, 3),
+                     "candidates": [(c["tile_class"], c["chunk_cols"], round(c["ms"], 4))
+                                    for c in info["candidates"]]},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,6 +285,8 @@ def main():
         f_ms = ev0.elapsed_time(ev1) / reps
         out["filter_only"] = {"ms": round(f_ms, 4), "nnz_cols_per_s": work / (f_ms * 1e-3)}
     g.close()
+    if not args.no_extra:
+        out["batched"] = [bench_batched(gift, W, torch, st) for st in ("f32", "bf16")]
 
     if not args.no_cpu_baseline:
         from oracle import oracle as O

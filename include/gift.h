@@ -211,6 +211,95 @@ gift_status gift_graph_export_normalised(const gift_graph *graph, double sigma, 
 gift_status gift_destroy_graph(gift_graph *graph, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Batched filtering: many resident graphs (designs of any sizes) filtered
+ * with the same terms and column count by one launch sequence, captured
+ * once into a HIP graph and replayed.  A batch is block-diagonal: every
+ * graph's result is the same as when filtered alone (the graphs share no
+ * rows, and each row is computed by the same arithmetic).
+ * ----------------------------------------------------------------------*/
+
+typedef struct gift_batch gift_batch;
+
+/* One graph's input and output for gift_batch_run (device pointers,
+ * row-major N_g x num_cols, leading dimensions in elements, same meaning as
+ * in gift_filter_placement). */
+typedef struct {
+  const void *x_in;          /* in_dtype [N_g][ld_in]                      */
+  int64_t ld_in;             /* >= num_cols                                */
+  void *y_out;               /* out_dtype [N_g][ld_out], not overlapping   */
+  int64_t ld_out;            /* >= num_cols                                */
+  const uint8_t *fixed_mask; /* uint8[N_g] or NULL                         */
+} gift_batch_io;
+
+#define GIFT_BATCH_MAX_CANDIDATES 8
+
+/* The schedule a batch runs and how it was chosen. */
+typedef struct {
+  int32_t num_graphs;
+  int32_t tile_class;   /* 0: row tiles of up to 2048 entries / 512 rows, rows
+                           longer than 256 entries alone; 1: 1024 / 256, 128 */
+  int32_t chunk_cols;   /* widest column chunk (one pass sequence per chunk)  */
+  int32_t tuned;        /* 0 default, 1 timed at creation, 2 from the cache  */
+  int64_t num_rows;     /* rows of all graphs (cells and star nodes)         */
+  int64_t nnz;          /* stored off-diagonal entries of all graphs         */
+  int64_t num_tiles;    /* tiles per SpMM pass                               */
+  int64_t device_bytes; /* device memory held by the batch itself           */
+  double tuned_ms;      /* replay time of the chosen schedule when timed     */
+  int32_t num_candidates;
+  int32_t reserved;
+  int32_t cand_tile_class[GIFT_BATCH_MAX_CANDIDATES];
+  int32_t cand_chunk_cols[GIFT_BATCH_MAX_CANDIDATES];
+  double cand_ms[GIFT_BATCH_MAX_CANDIDATES]; /* replay time of each candidate */
+} gift_batch_info;
+
+/*
+ * gift_batch_create -- plan, tune and capture the filter of num_graphs graphs
+ * (eq. proposed_filter applied to each graph's own signal).
+ *
+ *   graphs      host array of num_graphs >= 1 graphs on the current device,
+ *               all with the same storage type and with every sigma of
+ *               `terms` prepared.  The batch reads their device memory at
+ *               every run: they must outlive it and must not change.
+ *   terms       as in gift_filter_placement (copied).
+ *   num_cols    columns of every graph's signal (>= 1).
+ *   in_dtype, out_dtype   F32 or F64.
+ *   tune        0: default schedule (tile class 0, widest column chunk);
+ *               1: time every candidate schedule on zero inputs unless a
+ *               batch of the same shape class was tuned before in this
+ *               process, and keep the fastest; 2: always time.
+ *   stream      orders the batch's device memory and the tuning runs; the
+ *               call synchronises it before returning.
+ *
+ * Every SpMM pass of every graph and column chunk is one launch over the
+ * tiles of all graphs; the whole sequence is captured into a HIP graph (on an
+ * internal stream of default priority) that gift_batch_run replays.  The
+ * batch owns its signal buffers (rows of all graphs x the chunk width, see
+ * device_bytes).  Errors: GIFT_EINVAL (NULL pointers, sizes, mixed storage or
+ * devices, a sigma not prepared, bad tune), GIFT_EUNSUPPORTED (dtype, more
+ * than 2^31 - 1 tiles), GIFT_ENOMEM, GIFT_EDEVICE.  On error *out is NULL.
+ */
+gift_status gift_batch_create(const gift_graph *const *graphs, int32_t num_graphs,
+                              const gift_term *terms, int32_t num_terms, int32_t num_cols,
+                              int32_t in_dtype, int32_t out_dtype, int32_t tune, void *stream,
+                              gift_batch **out);
+
+/*
+ * gift_batch_run -- filter every graph of the batch: uploads the per-graph
+ * I/O pointers (io: host array of num_graphs entries, read during the call
+ * only; they may change from run to run) and replays the captured graph on
+ * `stream`.  Asynchronous.  Runs of one batch share its buffers, so they must
+ * be ordered (same stream, or event-ordered).  Errors: GIFT_EINVAL (NULL
+ * pointers, leading dimension < num_cols, wrong device), GIFT_EDEVICE.
+ */
+gift_status gift_batch_run(gift_batch *batch, const gift_batch_io *io, void *stream);
+
+gift_status gift_batch_get_info(const gift_batch *batch, gift_batch_info *info);
+
+/* Waits for the batch's last run, then releases it.  The graphs are not
+ * touched. */
+gift_status gift_batch_destroy(gift_batch *batch);
+
+/* ------------------------------------------------------------------------
  * Kernel timing (for benchmarks).
  * ----------------------------------------------------------------------*/
 

@@ -55,6 +55,28 @@ class BatchIO(C.Structure):
                 ("ld_out", C.c_int64), ("fixed_mask", C.c_void_p)]
 
 
+BATCH_MAX_CANDIDATES = 8
+
+
+class BatchInfo(C.Structure):
+    _fields_ = [
+        ("num_graphs", C.c_int32),
+        ("tile_class", C.c_int32),
+        ("chunk_cols", C.c_int32),
+        ("tuned", C.c_int32),
+        ("num_rows", C.c_int64),
+        ("nnz", C.c_int64),
+        ("num_tiles", C.c_int64),
+        ("device_bytes", C.c_int64),
+        ("tuned_ms", C.c_double),
+        ("num_candidates", C.c_int32),
+        ("reserved", C.c_int32),
+        ("cand_tile_class", C.c_int32 * BATCH_MAX_CANDIDATES),
+        ("cand_chunk_cols", C.c_int32 * BATCH_MAX_CANDIDATES),
+        ("cand_ms", C.c_double * BATCH_MAX_CANDIDATES),
+    ]
+
+
 class GiftError(RuntimeError):
     def __init__(self, status: int, where: str, message: str):
         self.status = status
@@ -80,9 +102,8 @@ SIGNATURES = {
                                     C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                                     C.POINTER(C.c_void_p)]),
     "gift_batch_run": (C.c_int, [C.c_void_p, C.POINTER(BatchIO), C.c_void_p]),
-    "gift_batch_schedule": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
-                                      C.POINTER(C.c_int64)]),
-    "gift_batch_destroy": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "gift_batch_get_info": (C.c_int, [C.c_void_p, C.POINTER(BatchInfo)]),
+    "gift_batch_destroy": (C.c_int, [C.c_void_p]),
     "gift_profile_enable": (C.c_int, [C.c_int32]),
     "gift_profile_collect": (C.c_int, [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                        C.POINTER(C.c_double), C.POINTER(C.c_double)]),

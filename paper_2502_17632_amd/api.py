@@ -174,6 +174,90 @@ def filter_placement(graph: Graph, sigma: Sequence[float], order: Sequence[int],
     return out
 
 
+class Batch:
+    """Many resident graphs filtered with the same terms and column count by
+    one captured launch sequence (``gift_batch_create``).  The graphs must
+    outlive the batch."""
+
+    def __init__(self, graphs: Sequence[Graph], sigma: Sequence[float], order: Sequence[int],
+                 alpha: Sequence[float], num_cols: int, *, in_dtype=torch.float32,
+                 out_dtype=torch.float32, tune: int = 1, stream=None):
+        if len(graphs) < 1:
+            raise ValueError("a batch needs at least one graph")
+        self._graphs = list(graphs)  # keeps the graphs alive
+        self._cells = [g.info()["num_cells"] for g in self._graphs]
+        self.num_cols = int(num_cols)
+        self.in_dtype, self.out_dtype = in_dtype, out_dtype
+        handles = (C.c_void_p * len(graphs))(*[g.handle for g in graphs])
+        terms = make_terms(sigma, order, alpha)
+        h = C.c_void_p()
+        L.check(L.lib().gift_batch_create(handles, len(graphs), terms, len(terms), self.num_cols,
+                                          TORCH_DTYPES[in_dtype], TORCH_DTYPES[out_dtype],
+                                          int(tune), _stream_handle(stream), C.byref(h)),
+                "gift_batch_create")
+        self._h = h
+
+    def info(self) -> dict:
+        inf = L.BatchInfo()
+        L.check(L.lib().gift_batch_get_info(self._h, C.byref(inf)), "gift_batch_get_info")
+        out = {k: getattr(inf, k) for k, _ in L.BatchInfo._fields_
+               if not k.startswith("cand_") and k != "reserved"}
+        n = inf.num_candidates
+        out["candidates"] = [{"tile_class": inf.cand_tile_class[i],
+                              "chunk_cols": inf.cand_chunk_cols[i], "ms": inf.cand_ms[i]}
+                             for i in range(n)]
+        return out
+
+    def run(self, xs: Sequence[torch.Tensor], outs: Optional[Sequence[torch.Tensor]] = None,
+            fixed: Optional[Sequence[Optional[torch.Tensor]]] = None, stream=None):
+        """Filters every graph's signal xs[g] (N_g x num_cols) into outs[g]."""
+        ng = len(self._graphs)
+        if len(xs) != ng:
+            raise ValueError(f"{len(xs)} signals for {ng} graphs")
+        if outs is None:
+            outs = [torch.empty((n, self.num_cols), dtype=self.out_dtype, device=x.device)
+                    for n, x in zip(self._cells, xs)]
+        io = (L.BatchIO * ng)()
+        keep = []
+        for g in range(ng):
+            x, y = xs[g], outs[g]
+            n = self._cells[g]
+            if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == self.in_dtype
+                    and x.dim() == 2 and tuple(x.shape) == (n, self.num_cols)
+                    and (n == 0 or x.stride(1) == 1)):
+                raise TypeError(f"xs[{g}] must be a {n} x {self.num_cols} {self.in_dtype} CUDA "
+                                "tensor with unit column stride")
+            if not (isinstance(y, torch.Tensor) and y.is_cuda and y.dtype == self.out_dtype
+                    and tuple(y.shape) == (n, self.num_cols) and (n == 0 or y.stride(1) == 1)):
+                raise TypeError(f"outs[{g}] must be a {n} x {self.num_cols} {self.out_dtype} "
+                                "CUDA tensor with unit column stride")
+            f = None if fixed is None else fixed[g]
+            if f is not None:
+                if not (f.is_cuda and f.dtype == torch.uint8 and f.numel() == n):
+                    raise TypeError(f"fixed[{g}] must be a uint8 CUDA tensor with {n} entries")
+                f = f.contiguous()
+                keep.append(f)
+            io[g].x_in = _ptr(x)
+            io[g].ld_in = x.stride(0) if n > 0 else self.num_cols
+            io[g].y_out = _ptr(y)
+            io[g].ld_out = y.stride(0) if n > 0 else self.num_cols
+            io[g].fixed_mask = _ptr(f)
+        L.check(L.lib().gift_batch_run(self._h, io, _stream_handle(stream)), "gift_batch_run")
+        return outs
+
+    def close(self):
+        if self._h is not None:
+            L.check(L.lib().gift_batch_destroy(self._h), "gift_batch_destroy")
+            self._h = None
+
+    def __del__(self):  # pragma: no cover - best effort
+        try:
+            if self._h is not None and torch.cuda.is_initialized():
+                self.close()
+        except Exception:
+            pass
+
+
 def profile_enable(on: bool = True):
     """Turn the library's per-launch event profiler on or off."""
     L.check(L.lib().gift_profile_enable(1 if on else 0), "gift_profile_enable")

@@ -43,10 +43,35 @@ def test_abi_version_and_status_strings():
     assert b"unknown" in lib.gift_status_string(99)
 
 
-def test_struct_layouts_match_header():
-    assert C.sizeof(L.GraphDesc) == 64
-    assert C.sizeof(L.Term) == 24
-    assert C.sizeof(L.GraphInfo) == 48
+STRUCTS = {"gift_graph_desc": L.GraphDesc, "gift_term": L.Term, "gift_graph_info": L.GraphInfo,
+           "gift_batch_io": L.BatchIO, "gift_batch_info": L.BatchInfo}
+
+
+def c_layouts(tmp_path):
+    """sizeof and every field offset of the header's structs, as the host C
+    compiler lays them out."""
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "gift.h"', "int main(void) {"]
+    for cname, py in STRUCTS.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "probe"
+    import subprocess
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-I", os.path.join(ROOT, "include"), str(src),
+                    "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    return {tuple(line.split()[:2]): int(line.split()[2]) for line in out.splitlines()}
+
+
+def test_struct_layouts_match_header(tmp_path):
+    lay = c_layouts(tmp_path)
+    for cname, py in STRUCTS.items():
+        assert lay[(cname, "size")] == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert lay[(cname, f)] == getattr(py, f).offset, (cname, f)
 
 
 def test_null_arguments_are_rejected_without_device_work():
@@ -106,3 +131,24 @@ def test_host_net_ptr_must_start_at_zero():
                     star_threshold=0, storage=0, num_sigmas=1, sigmas=sig.ctypes.data)
     out = C.c_void_p()
     assert lib.gift_build_graph(C.byref(d), None, C.byref(out)) == L.GIFT_EINVAL
+
+
+def test_batch_arguments_rejected_without_device_work():
+    lib = L.lib()
+    out = C.c_void_p()
+    terms = (L.Term * 1)()
+    assert lib.gift_batch_create(None, 1, terms, 1, 2, 0, 0, 1, None, C.byref(out)) == L.GIFT_EINVAL
+    graphs = (C.c_void_p * 1)()
+    assert lib.gift_batch_create(graphs, 0, terms, 1, 2, 0, 0, 1, None, C.byref(out)) == L.GIFT_EINVAL
+    assert lib.gift_batch_create(graphs, 1, terms, 0, 2, 0, 0, 1, None, C.byref(out)) == L.GIFT_EINVAL
+    assert lib.gift_batch_create(graphs, 1, terms, 1, 0, 0, 0, 1, None, C.byref(out)) == L.GIFT_EINVAL
+    assert lib.gift_batch_create(graphs, 1, terms, 1, 2, 2, 0, 1, None,
+                                 C.byref(out)) == L.GIFT_EUNSUPPORTED
+    assert lib.gift_batch_create(graphs, 1, terms, 1, 2, 0, 0, 3, None, C.byref(out)) == L.GIFT_EINVAL
+    assert lib.gift_batch_create(graphs, 1, terms, 1, 2, 0, 0, 1, None, None) == L.GIFT_EINVAL
+    assert out.value is None
+    io = (L.BatchIO * 1)()
+    assert lib.gift_batch_run(None, io, None) == L.GIFT_EINVAL
+    info = L.BatchInfo()
+    assert lib.gift_batch_get_info(None, C.byref(info)) == L.GIFT_EINVAL
+    assert lib.gift_batch_destroy(None) == L.GIFT_OK
