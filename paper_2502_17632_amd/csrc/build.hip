@@ -571,9 +571,27 @@ __global__ __launch_bounds__(kBlock) void k_sigma_values(const int32_t *row_ptr,
   __syncthreads();
   fill_segment_ids(loff, ns, seg);
   __syncthreads();
-  for (int i = threadIdx.x; i < n; i += kBlock) {
-    const int64_t p = p0 + i;
-    val[p] = Store<D>::from_f64((w[p] * ls[seg[i]]) * s[col[p]]);
+  // every load of the thread is issued before the first use: the entries'
+  // weights and columns, then the column scales.  Inactive slots read entry
+  // 0 (the arrays always hold at least one element) and use column 0 (the
+  // graph has rows, since it has this tile).
+  constexpr int kStage = (TCL::kCap + kBlock - 1) / kBlock;
+  double wv[kStage], sj[kStage];
+  int32_t cj[kStage];
+#pragma unroll
+  for (int k = 0; k < kStage; ++k) {
+    const int i = threadIdx.x + k * kBlock;
+    const int64_t p = i < n ? p0 + i : 0;
+    wv[k] = w[p];
+    const int32_t c = col[p];
+    cj[k] = i < n ? c : 0;
+  }
+#pragma unroll
+  for (int k = 0; k < kStage; ++k) sj[k] = s[cj[k]];
+#pragma unroll
+  for (int k = 0; k < kStage; ++k) {
+    const int i = threadIdx.x + k * kBlock;
+    if (i < n) val[p0 + i] = Store<D>::from_f64((wv[k] * ls[seg[i]]) * sj[k]);
   }
 }
 

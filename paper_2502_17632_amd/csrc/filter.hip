@@ -119,10 +119,11 @@ __device__ __forceinline__ int lanes_for(int rows) {
 
 // One SpMM pass over the tiles of this launch, one tile per block.
 //
-// Multi-row tile: every load is issued up front (inactive slots read entry 0
-// or row 0 of the tile's graph, always valid) so a thread has all its
+// Multi-row tile: every load is issued up front so a thread has all its
 // col/value, offset and diagonal loads in flight at once, then all its
-// gathers; the products are staged in LDS and each row is summed by a group
+// gathers (an unused slot reads entry 0, which exists even in a graph without
+// entries, and gathers row 0 of the tile's graph, not the column it read;
+// unused row slots read row r0); the products are staged in LDS and each row is summed by a group
 // of lanes sized to the tile's row count.  When the products would not fit
 // the LDS budget (wide signal rows) the entries (col, value) are staged
 // instead and the row groups gather the signal themselves.  Single long row:
@@ -214,7 +215,8 @@ __global__ __launch_bounds__(kBlock) void k_spmm(LaunchArgs l, const void *xin, 
     for (int k = 0; k < kStage; ++k) {
       const int i = tid + k * kBlock;
       const int q = i < n ? p0 + i : 0;
-      jj[k] = col[q];
+      const int32_t c = col[q];
+      jj[k] = i < n ? c : 0;  // an unused slot gathers row 0 of its graph
       vv[k] = S::load(val[q]);
     }
     constexpr int kRowIters = (TCL::kRows + 1 + kBlock - 1) / kBlock;
@@ -327,8 +329,8 @@ __global__ __launch_bounds__(kBlock) void k_spmm(LaunchArgs l, const void *xin, 
 }
 
 // x0 for the rows of one tile: cell rows are the caller's signal rounded to
-// the storage type, star rows the float64 mean of their net's cells (one
-// wave per star row).  A tile never mixes cell rows and star rows.
+// the storage type, star rows the float64 mean of their net's cells (a
+// group of lanes per star row).  A tile never mixes cell rows and star rows.
 template <int D, int C, bool kBatch>
 __global__ __launch_bounds__(kBlock) void k_prep(LaunchArgs l, int32_t in_dtype, int32_t col0,
                                                  void *x0v) {
@@ -347,21 +349,28 @@ __global__ __launch_bounds__(kBlock) void k_prep(LaunchArgs l, int32_t in_dtype,
     }
     return;
   }
-  const int lane = threadIdx.x & (kWave - 1);
-  for (int r = td.r0 + static_cast<int>(threadIdx.x) / kWave; r < td.r1; r += kBlock / kWave) {
-    const int32_t p0 = row_ptr[r], p1 = row_ptr[r + 1];
+  // star rows (more than 16 entries each): a group of at least 16 lanes per
+  // row, more when the tile has few rows
+  const int nrows = td.r1 - td.r0;
+  const int G = lanes_for(nrows) > 16 ? lanes_for(nrows) : 16;
+  const int lane = threadIdx.x & (G - 1);
+  for (int base = 0; base < nrows; base += kBlock / G) {
+    const int rr = base + static_cast<int>(threadIdx.x) / G;
+    const bool live = rr < nrows;
+    const int r = td.r0 + (live ? rr : 0);
+    const int32_t p0 = row_ptr[r], p1 = live ? row_ptr[r + 1] : p0;
     double s[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) s[c] = 0.0;
-    for (int32_t q = p0 + lane; q < p1; q += kWave) {
+    for (int32_t q = p0 + lane; q < p1; q += G) {
       const int64_t j = col[q];
 #pragma unroll
       for (int c = 0; c < C; ++c) s[c] += load_in(io.x_in, in_dtype, j * io.ld_in + col0 + c);
     }
 #pragma unroll
     for (int c = 0; c < C; ++c)
-      for (int off = kWave / 2; off > 0; off >>= 1) s[c] += __shfl_xor(s[c], off);
-    if (lane == 0) {
+      for (int off = G >> 1; off > 0; off >>= 1) s[c] += __shfl_xor(s[c], off);
+    if (live && lane == 0) {
       const double m = static_cast<double>(p1 - p0);
 #pragma unroll
       for (int c = 0; c < C; ++c)
