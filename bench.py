@@ -171,6 +171,107 @@ def bench_batched(gift, W, torch, storage, reps=10):
     }
 
 
+def bench_serving(gift, W, torch, n_requests=1000, pool=24, load=0.7):
+    """Poisson stream of filter requests (2 columns, sigma 4, orders 1, 2, 4, 8)
+    over a pool of designs with log-uniform 5k-2M movable cells: serial
+    per-request execution (build on first use, filter, wait) against the
+    serving engine, both from an empty graph cache, at an offered load of
+    `load` times the measured serial capacity.  Latency is measured from each
+    request's arrival time to its completion on the device."""
+    import numpy as np
+    terms = ([4.0] * 4, [1, 2, 4, 8], [0.25] * 4)
+    sizes = W.serving_sizes(pool)
+    log(f"[bench] serving: generating {pool} designs")
+    nls = [W.sized(n, seed=5000 + i) for i, n in enumerate(sizes)]
+    xs = [torch.tensor(W.make_signal(nl, seed=5000 + i), dtype=torch.float32, device="cuda")
+          for i, nl in enumerate(nls)]
+    design_of = np.random.default_rng(4244).integers(0, pool, size=n_requests)
+    torch.cuda.synchronize()
+
+    def wait_until(t):
+        while True:
+            d = t - time.perf_counter()
+            if d <= 0:
+                return
+            if d > 2e-3:
+                time.sleep(d - 1e-3)
+
+    def serial(arrivals):
+        cache, outs, lat = {}, [], []
+        t0 = time.perf_counter()
+        for j, d in enumerate(design_of):
+            ta = t0 + arrivals[j] if arrivals is not None else time.perf_counter()
+            if arrivals is not None:
+                wait_until(ta)
+            g = cache.get(d)
+            if g is None:
+                nl = nls[d]
+                g = cache[d] = gift.build_graph(nl.num_cells, nl.net_ptr, nl.pin_cell,
+                                                star_threshold=16, sigmas=[4.0])
+            outs.append(gift.filter_placement(g, *terms, xs[d]))
+            torch.cuda.synchronize()
+            lat.append((time.perf_counter() - ta) * 1e3)
+        span = time.perf_counter() - t0
+        for g in cache.values():
+            g.close()
+        torch.cuda.synchronize()
+        return np.array(lat), span, outs
+
+    log(f"[bench] serving: serial capacity ({n_requests} requests back to back)")
+    _, busy, _ = serial(None)
+    rate = load * n_requests / busy
+    arrivals = W.poisson_arrivals(n_requests, rate)
+    log(f"[bench] serving: serial at {rate:.0f} requests/s")
+    lat_s, span_s, outs_s = serial(arrivals)
+
+    def served(arrivals):
+        srv = gift.Server(*terms, num_cols=2, hbm_budget_bytes=200 << 30, max_inflight=64,
+                          num_streams=4, num_builders=2, max_batch=32)
+        t0 = time.perf_counter()
+        subs = []
+        for j, d in enumerate(design_of):
+            ta = t0 + arrivals[j] if arrivals is not None else time.perf_counter()
+            if arrivals is not None:
+                wait_until(ta)
+            nl = nls[d]
+            lag = (time.perf_counter() - ta) * 1e3
+            t, y = srv.submit(int(d), nl.num_cells, nl.net_ptr, nl.pin_cell, xs[d])
+            subs.append((t, y, lag))
+        lat = np.array([lag + srv.wait(t)["latency_ms"] for t, _, lag in subs])
+        span = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        return lat, span, [y for _, y, _ in subs], st
+
+    log("[bench] serving: engine")
+    lat_v, span_v, outs_v, st = served(arrivals)
+    same = all(torch.equal(a, b) for a, b in zip(outs_s, outs_v))
+    log("[bench] serving: engine, all requests at once")
+    _, span_sat, outs_sat, st_sat = served(None)
+    same = same and all(torch.equal(a, b) for a, b in zip(outs_s, outs_sat))
+
+    def summary(lat, span):
+        return {"p50_ms": round(float(np.percentile(lat, 50)), 3),
+                "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                "mean_ms": round(float(lat.mean()), 3), "makespan_s": round(span, 3),
+                "throughput_rps": round(n_requests / span, 1)}
+    return {
+        "workload": f"{n_requests} requests, Poisson arrivals (seed 4242) at {load} x serial "
+                    f"capacity, over {pool} designs with log-uniform 5k-2M movable cells "
+                    "(medium generator, seeds 5000+i), 2 columns, sigma 4, orders 1,2,4,8",
+        "rate_rps": round(rate, 1), "serial_capacity_rps": round(n_requests / busy, 1),
+        "serial": summary(lat_s, span_s), "served": summary(lat_v, span_v),
+        "served_batches": st["batches"],
+        "served_mean_batch": round(st["batched_requests"] / max(st["batches"], 1), 2),
+        "builds": st["builds"], "evictions": st["evictions"],
+        "saturated": {"serial_throughput_rps": round(n_requests / busy, 1),
+                      "served_throughput_rps": round(n_requests / span_sat, 1),
+                      "served_mean_batch": round(st_sat["batched_requests"] /
+                                                 max(st_sat["batches"], 1), 2)},
+        "results_equal_to_serial": bool(same),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -287,6 +388,7 @@ def main():
     g.close()
     if not args.no_extra:
         out["batched"] = [bench_batched(gift, W, torch, st) for st in ("f32", "bf16")]
+        out["serving"] = bench_serving(gift, W, torch)
 
     if not args.no_cpu_baseline:
         from oracle import oracle as O

@@ -148,8 +148,11 @@ typedef struct {
  * normalised values a_ij = (w_ij s_i) s_j and diagonal (sigma s_i) s_i with
  * s_i = 1/sqrt(d_i + sigma) (s_i = 0 when d_i + sigma = 0), rounded once to
  * the storage type.  The structure, weights and degrees are deterministic.
- * The call synchronises `stream` (it reads sizes back) and returns after the
- * graph is complete.  Errors: GIFT_EINVAL for a malformed netlist (pin out of
+ * The call synchronises `stream` while it reads sizes back and returns with
+ * the last kernels (merge, normalisation) still enqueued on `stream`: work on
+ * `stream` may use the graph at once; work on another stream must first wait
+ * for `stream` (synchronise it, or wait on an event recorded on it).
+ * Errors: GIFT_EINVAL for a malformed netlist (pin out of
  * range, net_ptr not starting at 0 or decreasing), negative sizes, sigma < 0,
  * num_sigmas < 1 or bad enums; GIFT_ENOMEM; GIFT_EDEVICE.  On error *out is
  * NULL and nothing is leaked.
@@ -183,7 +186,8 @@ gift_status gift_filter_placement(const gift_graph *graph, const gift_term *term
                                   int64_t ld_out, int32_t out_dtype,
                                   const uint8_t *fixed_mask, void *stream);
 
-/* Prepare one more self-loop weight (sigma >= 0).  No-op if already there. */
+/* Prepare one more self-loop weight (sigma >= 0).  No-op if already there.
+ * Asynchronous on `stream`, like the tail of gift_build_graph. */
 gift_status gift_graph_add_sigma(gift_graph *graph, double sigma, void *stream);
 
 gift_status gift_graph_get_info(const gift_graph *graph, gift_graph_info *info);
@@ -298,6 +302,113 @@ gift_status gift_batch_get_info(const gift_batch *batch, gift_batch_info *info);
 /* Waits for the batch's last run, then releases it.  The graphs are not
  * touched. */
 gift_status gift_batch_destroy(gift_batch *batch);
+
+/* ------------------------------------------------------------------------
+ * Request serving: filter requests for many designs with graphs kept
+ * resident, admission by a device-memory budget and continuous batching.
+ * ----------------------------------------------------------------------*/
+
+typedef struct gift_server gift_server;
+
+/* Server options.  Every request uses the same filter (terms), column count
+ * and data types. */
+typedef struct {
+  int64_t hbm_budget_bytes; /* device memory for resident graphs, builds and
+                               filter work (>= 1 MiB)                        */
+  int32_t max_inflight;     /* requests admitted at once (>= 1)              */
+  int32_t num_streams;      /* filter streams, default priority (1..16)      */
+  int32_t num_builders;     /* build threads, one stream each (1..16)        */
+  int32_t max_batch;        /* requests per launch sequence (>= 1)           */
+  int64_t max_batch_rows;   /* graph rows per launch; a larger request runs
+                               alone (>= 1)                                  */
+  int32_t storage;          /* gift_dtype of the graphs built               */
+  int32_t weight_model;     /* gift_weight_model                            */
+  int64_t star_threshold;   /* as in gift_graph_desc                        */
+  int32_t num_cols;         /* signal columns of every request (>= 1)       */
+  int32_t in_dtype;         /* F32 or F64                                   */
+  int32_t out_dtype;        /* F32 or F64                                   */
+  int32_t num_terms;        /* 1..64                                        */
+  const gift_term *terms;   /* copied                                       */
+} gift_server_config;
+
+/* One filter request.  The netlist (host memory) is read only if the design's
+ * graph is not resident; it must stay valid until gift_server_wait returns
+ * for the request.  The signals are device buffers as in
+ * gift_filter_placement, N x num_cols with leading dimensions. */
+typedef struct {
+  uint64_t design_id; /* key of the resident graph: equal ids must name
+                         equal netlists                                     */
+  int64_t num_cells;
+  int64_t num_nets;
+  const int64_t *net_ptr;    /* host int64[num_nets + 1]                     */
+  const int32_t *pin_cell;   /* host int32[net_ptr[num_nets]]               */
+  const void *x_in;          /* device, in_dtype [num_cells][ld_in]         */
+  int64_t ld_in;
+  void *y_out;               /* device, out_dtype [num_cells][ld_out]       */
+  int64_t ld_out;
+  const uint8_t *fixed_mask; /* device uint8[num_cells] or NULL             */
+} gift_request;
+
+typedef struct {
+  int32_t status;     /* gift_status of the request                        */
+  int32_t built;      /* 1 if this request built its design's graph        */
+  double latency_ms;  /* submit -> result complete on the device           */
+  double queue_ms;    /* submit -> admitted                                */
+  double service_ms;  /* admitted -> complete                              */
+} gift_request_result;
+
+typedef struct {
+  int64_t submitted, completed, failed;
+  int64_t builds, evictions;
+  int64_t batches;          /* launch sequences                              */
+  int64_t batched_requests; /* requests over all launch sequences           */
+  int64_t resident_graphs, resident_bytes;
+  int64_t reserved_bytes, peak_reserved_bytes; /* budget accounting         */
+  double p50_ms, p99_ms, mean_ms, max_ms;      /* latency of completed ones */
+  double elapsed_s;         /* first submit -> last completion              */
+} gift_server_stats;
+
+/*
+ * gift_server_create -- start a server on the current device: a dispatcher
+ * thread and num_builders build threads.
+ *
+ * A submitted request is admitted when fewer than max_inflight requests are
+ * admitted and its memory fits the budget: filter buffers, plus, if its
+ * design is not resident, a bound on the graph and on the build's scratch
+ * computed from the pin counts.  To make room the server evicts resident
+ * graphs that no admitted request uses, least recently used first; a request
+ * that does not fit yet waits without blocking later ones that do, and one
+ * that can never fit fails with GIFT_ENOMEM.  A missing graph is built on a
+ * builder's stream (eq. A_formulation) and stays resident.  Requests whose
+ * graphs are resident are grouped by size (rows within a factor of two, at
+ * most max_batch requests and max_batch_rows rows) and filtered
+ * (eq. proposed_filter) by one launch sequence on the least loaded filter
+ * stream; each result is computed with the same arithmetic as
+ * gift_filter_placement on that graph alone.  Requests that arrive while
+ * others run join later launches, so their work overlaps on the device.
+ * Errors: GIFT_EINVAL (bad options), GIFT_EUNSUPPORTED, GIFT_EDEVICE.
+ */
+gift_status gift_server_create(const gift_server_config *config, gift_server **out);
+
+/* Queue one request; *ticket identifies it.  Every ticket must be waited for
+ * (gift_server_wait releases it).  Errors: GIFT_EINVAL, GIFT_EBUSY (server
+ * stopping). */
+gift_status gift_server_submit(gift_server *server, const gift_request *request,
+                               uint64_t *ticket);
+
+/* Wait until the request is complete on the device (timeout_s < 0: no
+ * limit).  Returns the request's status (GIFT_EBUSY if the timeout expired;
+ * the ticket stays valid then) and fills *result (may be NULL). */
+gift_status gift_server_wait(gift_server *server, uint64_t ticket, double timeout_s,
+                             gift_request_result *result);
+
+/* Counters and latency percentiles of the requests completed since the last
+ * reset; reset != 0 starts a new window. */
+gift_status gift_server_get_stats(gift_server *server, int32_t reset, gift_server_stats *out);
+
+/* Finish every submitted request, stop the threads and release every
+ * resident graph. */
+gift_status gift_server_destroy(gift_server *server);
 
 /* ------------------------------------------------------------------------
  * Kernel timing (for benchmarks).

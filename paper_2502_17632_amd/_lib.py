@@ -77,6 +77,57 @@ class BatchInfo(C.Structure):
     ]
 
 
+class ServerConfig(C.Structure):
+    _fields_ = [
+        ("hbm_budget_bytes", C.c_int64),
+        ("max_inflight", C.c_int32),
+        ("num_streams", C.c_int32),
+        ("num_builders", C.c_int32),
+        ("max_batch", C.c_int32),
+        ("max_batch_rows", C.c_int64),
+        ("storage", C.c_int32),
+        ("weight_model", C.c_int32),
+        ("star_threshold", C.c_int64),
+        ("num_cols", C.c_int32),
+        ("in_dtype", C.c_int32),
+        ("out_dtype", C.c_int32),
+        ("num_terms", C.c_int32),
+        ("terms", C.c_void_p),
+    ]
+
+
+class Request(C.Structure):
+    _fields_ = [
+        ("design_id", C.c_uint64),
+        ("num_cells", C.c_int64),
+        ("num_nets", C.c_int64),
+        ("net_ptr", C.c_void_p),
+        ("pin_cell", C.c_void_p),
+        ("x_in", C.c_void_p),
+        ("ld_in", C.c_int64),
+        ("y_out", C.c_void_p),
+        ("ld_out", C.c_int64),
+        ("fixed_mask", C.c_void_p),
+    ]
+
+
+class RequestResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("built", C.c_int32), ("latency_ms", C.c_double),
+                ("queue_ms", C.c_double), ("service_ms", C.c_double)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [
+        ("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
+        ("builds", C.c_int64), ("evictions", C.c_int64),
+        ("batches", C.c_int64), ("batched_requests", C.c_int64),
+        ("resident_graphs", C.c_int64), ("resident_bytes", C.c_int64),
+        ("reserved_bytes", C.c_int64), ("peak_reserved_bytes", C.c_int64),
+        ("p50_ms", C.c_double), ("p99_ms", C.c_double), ("mean_ms", C.c_double),
+        ("max_ms", C.c_double), ("elapsed_s", C.c_double),
+    ]
+
+
 class GiftError(RuntimeError):
     def __init__(self, status: int, where: str, message: str):
         self.status = status
@@ -104,6 +155,12 @@ SIGNATURES = {
     "gift_batch_run": (C.c_int, [C.c_void_p, C.POINTER(BatchIO), C.c_void_p]),
     "gift_batch_get_info": (C.c_int, [C.c_void_p, C.POINTER(BatchInfo)]),
     "gift_batch_destroy": (C.c_int, [C.c_void_p]),
+    "gift_server_create": (C.c_int, [C.POINTER(ServerConfig), C.POINTER(C.c_void_p)]),
+    "gift_server_submit": (C.c_int, [C.c_void_p, C.POINTER(Request), C.POINTER(C.c_uint64)]),
+    "gift_server_wait": (C.c_int, [C.c_void_p, C.c_uint64, C.c_double,
+                                   C.POINTER(RequestResult)]),
+    "gift_server_get_stats": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(ServerStats)]),
+    "gift_server_destroy": (C.c_int, [C.c_void_p]),
     "gift_profile_enable": (C.c_int, [C.c_int32]),
     "gift_profile_collect": (C.c_int, [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                        C.POINTER(C.c_double), C.POINTER(C.c_double)]),

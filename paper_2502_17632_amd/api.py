@@ -258,6 +258,107 @@ class Batch:
             pass
 
 
+class Server:
+    """The library's request-serving engine (``gift_server_create``): designs'
+    graphs stay resident, requests are admitted by a device-memory budget and
+    batched continuously.  ``submit`` returns a ticket; ``wait`` returns the
+    request's timing."""
+
+    def __init__(self, sigma: Sequence[float], order: Sequence[int], alpha: Sequence[float],
+                 num_cols: int, *, hbm_budget_bytes: int = 200 << 30, max_inflight: int = 64,
+                 num_streams: int = 4, num_builders: int = 2, max_batch: int = 32,
+                 max_batch_rows: int = 4_000_000, storage: str = "f32",
+                 weight_model: str = "inv_m1", star_threshold: int = 16,
+                 in_dtype=torch.float32, out_dtype=torch.float32):
+        self._terms = make_terms(sigma, order, alpha)
+        cfg = L.ServerConfig()
+        cfg.hbm_budget_bytes = int(hbm_budget_bytes)
+        cfg.max_inflight = int(max_inflight)
+        cfg.num_streams = int(num_streams)
+        cfg.num_builders = int(num_builders)
+        cfg.max_batch = int(max_batch)
+        cfg.max_batch_rows = int(max_batch_rows)
+        cfg.storage = DTYPES[storage]
+        cfg.weight_model = WEIGHT_MODELS[weight_model]
+        cfg.star_threshold = int(star_threshold)
+        cfg.num_cols = int(num_cols)
+        cfg.in_dtype = TORCH_DTYPES[in_dtype]
+        cfg.out_dtype = TORCH_DTYPES[out_dtype]
+        cfg.num_terms = len(self._terms)
+        cfg.terms = C.addressof(self._terms)
+        self.num_cols, self.in_dtype, self.out_dtype = int(num_cols), in_dtype, out_dtype
+        h = C.c_void_p()
+        L.check(L.lib().gift_server_create(C.byref(cfg), C.byref(h)), "gift_server_create")
+        self._h = h
+        self._keep = {}  # ticket -> buffers that must outlive the request
+
+    def submit(self, design_id: int, num_cells: int, net_ptr: np.ndarray, pin_cell: np.ndarray,
+               x: torch.Tensor, out: Optional[torch.Tensor] = None,
+               fixed: Optional[torch.Tensor] = None):
+        """Queue one request; returns (ticket, output tensor)."""
+        net_ptr = np.ascontiguousarray(net_ptr, dtype=np.int64)
+        pin_cell = np.ascontiguousarray(pin_cell, dtype=np.int32)
+        if net_ptr.ndim != 1 or net_ptr.shape[0] < 1 or int(net_ptr[-1]) != pin_cell.shape[0]:
+            raise ValueError("net_ptr must hold num_nets + 1 offsets ending at len(pin_cell)")
+        n = int(num_cells)
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == self.in_dtype
+                and tuple(x.shape) == (n, self.num_cols) and (n == 0 or x.stride(1) == 1)):
+            raise TypeError(f"x must be a {n} x {self.num_cols} {self.in_dtype} CUDA tensor "
+                            "with unit column stride")
+        if out is None:
+            out = torch.empty((n, self.num_cols), dtype=self.out_dtype, device=x.device)
+        if not (out.is_cuda and out.dtype == self.out_dtype and tuple(out.shape) ==
+                (n, self.num_cols) and (n == 0 or out.stride(1) == 1)):
+            raise TypeError("out does not match the request")
+        if fixed is not None:
+            if not (fixed.is_cuda and fixed.dtype == torch.uint8 and fixed.numel() == n):
+                raise TypeError("fixed must be a uint8 CUDA tensor with one entry per cell")
+            fixed = fixed.contiguous()
+        r = L.Request()
+        r.design_id = int(design_id)
+        r.num_cells = n
+        r.num_nets = int(net_ptr.shape[0]) - 1
+        r.net_ptr = _ptr(net_ptr)
+        r.pin_cell = _ptr(pin_cell) if pin_cell.shape[0] else _ptr(np.zeros(1, np.int32))
+        r.x_in = _ptr(x)
+        r.ld_in = x.stride(0) if n else self.num_cols
+        r.y_out = _ptr(out)
+        r.ld_out = out.stride(0) if n else self.num_cols
+        r.fixed_mask = _ptr(fixed)
+        t = C.c_uint64()
+        L.check(L.lib().gift_server_submit(self._h, C.byref(r), C.byref(t)), "gift_server_submit")
+        self._keep[t.value] = (net_ptr, pin_cell, x, out, fixed)
+        return t.value, out
+
+    def wait(self, ticket: int, timeout_s: float = -1.0) -> dict:
+        res = L.RequestResult()
+        st = L.lib().gift_server_wait(self._h, int(ticket), float(timeout_s), C.byref(res))
+        if st == L.GIFT_EBUSY:
+            raise TimeoutError(f"request {ticket} not finished")
+        self._keep.pop(int(ticket), None)
+        L.check(st, "gift_server_wait")
+        return {k: getattr(res, k) for k, _ in L.RequestResult._fields_}
+
+    def stats(self, reset: bool = False) -> dict:
+        st = L.ServerStats()
+        L.check(L.lib().gift_server_get_stats(self._h, 1 if reset else 0, C.byref(st)),
+                "gift_server_get_stats")
+        return {k: getattr(st, k) for k, _ in L.ServerStats._fields_}
+
+    def close(self):
+        if self._h is not None:
+            L.check(L.lib().gift_server_destroy(self._h), "gift_server_destroy")
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):  # pragma: no cover - best effort
+        try:
+            if self._h is not None and torch.cuda.is_initialized():
+                self.close()
+        except Exception:
+            pass
+
+
 def profile_enable(on: bool = True):
     """Turn the library's per-launch event profiler on or off."""
     L.check(L.lib().gift_profile_enable(1 if on else 0), "gift_profile_enable")

@@ -13,6 +13,7 @@
 // replays and keeps the fastest; the choice is cached per shape class.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <new>
@@ -331,6 +332,159 @@ gift_status autotune(gift_batch *b, Candidate *best) {
 }
 
 }  // namespace
+
+PinnedRing::~PinnedRing() {
+  for (int i = 0; i < kSlots; ++i) {
+    if (ev_[i]) {
+      (void)hipEventSynchronize(ev_[i]);
+      (void)hipEventDestroy(ev_[i]);
+    }
+    if (buf_[i]) (void)hipHostFree(buf_[i]);
+  }
+}
+
+gift_status PinnedRing::acquire(size_t bytes, void **p) {
+  const int s = next_;
+  next_ = (next_ + 1) % kSlots;
+  if (!ev_[s]) GIFT_HIP(hipEventCreateWithFlags(&ev_[s], hipEventDisableTiming));
+  GIFT_HIP(hipEventSynchronize(ev_[s]));
+  if (cap_[s] < bytes) {
+    if (buf_[s]) (void)hipHostFree(buf_[s]);
+    buf_[s] = nullptr;
+    cap_[s] = 0;
+    const size_t want = bytes < 65536 ? 65536 : bytes * 2;
+    GIFT_HIP(hipHostMalloc(&buf_[s], want));
+    cap_[s] = want;
+  }
+  cur_ = s;
+  *p = buf_[s];
+  return GIFT_OK;
+}
+
+gift_status PinnedRing::release(hipStream_t st) {
+  if (cur_ < 0) return GIFT_OK;
+  GIFT_HIP(hipEventRecord(ev_[cur_], st));
+  cur_ = -1;
+  return GIFT_OK;
+}
+
+size_t dynamic_batch_bytes(const gift_graph *const *graphs, int32_t n, int32_t storage,
+                           int32_t num_terms, int32_t num_cols) {
+  FilterPlan pl;
+  pl.storage = storage;
+  int64_t tiles = 0;
+  for (int32_t g = 0; g < n; ++g) {
+    pl.R += graphs[g]->num_rows;
+    tiles += graphs[g]->num_tiles[0] + graphs[g]->num_tiles_cells[0];
+  }
+  // every term but one may keep a saved iterate
+  const size_t rb = dtype_size(storage) * static_cast<size_t>(chunk_width(num_cols)) *
+                    static_cast<size_t>(pl.R);
+  return (3 + static_cast<size_t>(num_terms)) * (rb + 256) +
+         static_cast<size_t>(tiles) * (sizeof(TileDesc) + 4) +
+         static_cast<size_t>(n) * (kMaxTerms * sizeof(GraphDev) + 2 * sizeof(ConcatSrc)) + 4096;
+}
+
+gift_status enqueue_dynamic_batch(const gift_graph *const *graphs, const GraphIO *ios, int32_t n,
+                                  const gift_term *terms, int32_t nt, int32_t num_cols,
+                                  int32_t in_dt, int32_t out_dt, hipStream_t st,
+                                  PinnedRing &ring) {
+  if (n < 1) return GIFT_OK;
+  std::vector<std::vector<PlanGroup>> per(n);
+  for (int32_t g = 0; g < n; ++g) GIFT_TRY(plan_groups(graphs[g], terms, nt, &per[g]));
+  const size_t ngr = per[0].size();
+  constexpr int c = 0;
+  std::vector<GraphDev> table(ngr * n);
+  std::vector<ConcatSrc> sa, sf;
+  FilterPlan pl;
+  pl.storage = graphs[0]->storage;
+  int64_t most_a = 0, most_f = 0;
+  for (int32_t g = 0; g < n; ++g) {
+    const gift_graph *gr = graphs[g];
+    if (gr->storage != pl.storage)
+      return set_error(GIFT_EINVAL, "graph %d: storage differs from graph 0", g);
+    GraphIO io = ios[g];
+    io.num_cells = gr->num_cells;
+    for (size_t k = 0; k < ngr; ++k)
+      table[k * n + g] = GraphDev{gr->row_ptr, gr->col, per[g][k].val, per[g][k].diag, pl.R, io};
+    if (gr->num_tiles[c] > 0) {
+      sa.push_back(ConcatSrc{gr->tiles[c], gr->num_tiles[c], pl.num_tiles, g});
+      pl.num_tiles += gr->num_tiles[c];
+      most_a = std::max(most_a, gr->num_tiles[c]);
+    }
+    if (gr->num_tiles_cells[c] > 0) {
+      sf.push_back(ConcatSrc{gr->tiles[c], gr->num_tiles_cells[c], pl.num_final_tiles, g});
+      pl.num_final_tiles += gr->num_tiles_cells[c];
+      most_f = std::max(most_f, gr->num_tiles_cells[c]);
+    }
+    pl.R += gr->num_rows;
+    pl.nnz += gr->nnz;
+    pl.cell_rows += gr->num_cells;
+    pl.nnz_cells += gr->nnz_cells;
+  }
+  if (pl.num_tiles == 0) return GIFT_OK;
+  if (pl.num_tiles >= (int64_t(1) << 31) - 1)
+    return set_error(GIFT_EUNSUPPORTED, "batch has %lld tiles (limit 2^31 - 1)",
+                     static_cast<long long>(pl.num_tiles));
+
+  const size_t tb = sizeof(GraphDev) * table.size();
+  const size_t ab = sizeof(ConcatSrc) * sa.size(), fb = sizeof(ConcatSrc) * sf.size();
+  void *h = nullptr;
+  GIFT_TRY(ring.acquire(tb + ab + fb, &h));
+  unsigned char *hb = static_cast<unsigned char *>(h);
+  std::memcpy(hb, table.data(), tb);
+  std::memcpy(hb + tb, sa.data(), ab);
+  if (fb) std::memcpy(hb + tb + ab, sf.data(), fb);
+  Scratch sc(st);
+  unsigned char *up = nullptr;
+  GIFT_TRY(sc.get(&up, tb + ab + fb, "batch table"));
+  GIFT_HIP(hipMemcpyAsync(up, hb, tb + ab + fb, hipMemcpyHostToDevice, st));
+  GIFT_TRY(ring.release(st));
+  const GraphDev *dtable = reinterpret_cast<const GraphDev *>(up);
+  TileDesc *ta = nullptr, *tf = nullptr;
+  int32_t *ga = nullptr, *gf = nullptr;
+  GIFT_TRY(sc.get(&ta, pl.num_tiles, "batch tiles"));
+  GIFT_TRY(sc.get(&ga, pl.num_tiles, "batch tile graphs"));
+  GIFT_TRY(sc.get(&tf, pl.num_final_tiles + 1, "batch final tiles"));
+  GIFT_TRY(sc.get(&gf, pl.num_final_tiles + 1, "batch final tile graphs"));
+  auto gy = [](int64_t most) {
+    return static_cast<unsigned>(std::min<int64_t>((most + kBlock - 1) / kBlock, 64));
+  };
+  const dim3 grid_a(static_cast<unsigned>(sa.size()), gy(most_a));
+  k_concat_tiles<<<grid_a, kBlock, 0, st>>>(reinterpret_cast<const ConcatSrc *>(up + tb), ta, ga);
+  GIFT_TRY(check_launch("k_concat_tiles"));
+  if (!sf.empty()) {
+    const dim3 grid_f(static_cast<unsigned>(sf.size()), gy(most_f));
+    k_concat_tiles<<<grid_f, kBlock, 0, st>>>(reinterpret_cast<const ConcatSrc *>(up + tb + ab),
+                                              tf, gf);
+    GIFT_TRY(check_launch("k_concat_tiles"));
+  }
+
+  pl.tile_class = c;
+  pl.tiles = ta;
+  pl.tile_graph = ga;
+  pl.final_tiles = tf;
+  pl.final_tile_graph = gf;
+  pl.groups = per[0];
+  for (size_t k = 0; k < ngr; ++k) pl.groups[k].graphs = dtable + k * n;
+  pl.terms = terms;
+  pl.num_terms = nt;
+  pl.in_dtype = in_dt;
+  pl.out_dtype = out_dt;
+  pl.profile = false;
+  const int widest = chunk_width(num_cols);
+  unsigned char *buf = nullptr;
+  GIFT_TRY(sc.get(&buf, chunk_buffer_bytes(pl, widest), "batch signal buffers"));
+  for (int32_t col0 = 0; col0 < num_cols;) {
+    const int C = chunk_width(num_cols - col0);
+    ChunkBuffers bf;
+    carve_chunk_buffers(pl, C, buf, &bf);
+    GIFT_TRY(enqueue_filter_chunk(pl, bf, C, col0, st));
+    col0 += C;
+  }
+  return GIFT_OK;
+}
+
 }  // namespace gift
 
 extern "C" gift_status gift_batch_create(const gift_graph *const *graphs, int32_t num_graphs,

@@ -84,4 +84,38 @@ size_t carve_chunk_buffers(const FilterPlan &pl, int C, unsigned char *base, Chu
 gift_status enqueue_filter_chunk(const FilterPlan &pl, const ChunkBuffers &bf, int C,
                                  int32_t col0, hipStream_t st);
 
+// Pinned host staging for small uploads: a ring of buffers, each reused only
+// after the copy that last read it has run.
+class PinnedRing {
+ public:
+  PinnedRing() = default;
+  PinnedRing(const PinnedRing &) = delete;
+  PinnedRing &operator=(const PinnedRing &) = delete;
+  ~PinnedRing();
+  // A pinned buffer of at least `bytes` (waits for the slot's previous copy).
+  gift_status acquire(size_t bytes, void **p);
+  // The buffer from the last acquire is read by work enqueued on `st` so far.
+  gift_status release(hipStream_t st);
+
+ private:
+  static constexpr int kSlots = 4;
+  void *buf_[kSlots] = {};
+  size_t cap_[kSlots] = {};
+  hipEvent_t ev_[kSlots] = {};
+  int next_ = 0, cur_ = -1;
+};
+
+// Enqueues the filter of n graphs, each with its own I/O, as one uncaptured
+// launch sequence on `st`: every pass is one launch over the tiles of all
+// graphs (tile class 0, widest column chunks: the arithmetic of filtering
+// each graph alone).  Device scratch comes from the stream-ordered cache, the
+// per-graph table goes through `ring`.
+gift_status enqueue_dynamic_batch(const gift_graph *const *graphs, const GraphIO *ios, int32_t n,
+                                  const gift_term *terms, int32_t nt, int32_t num_cols,
+                                  int32_t in_dt, int32_t out_dt, hipStream_t st,
+                                  PinnedRing &ring);
+// Device bytes enqueue_dynamic_batch takes from the cache for these graphs.
+size_t dynamic_batch_bytes(const gift_graph *const *graphs, int32_t n, int32_t storage,
+                           int32_t num_terms, int32_t num_cols);
+
 }  // namespace gift

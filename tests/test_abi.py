@@ -44,7 +44,9 @@ def test_abi_version_and_status_strings():
 
 
 STRUCTS = {"gift_graph_desc": L.GraphDesc, "gift_term": L.Term, "gift_graph_info": L.GraphInfo,
-           "gift_batch_io": L.BatchIO, "gift_batch_info": L.BatchInfo}
+           "gift_batch_io": L.BatchIO, "gift_batch_info": L.BatchInfo,
+           "gift_server_config": L.ServerConfig, "gift_request": L.Request,
+           "gift_request_result": L.RequestResult, "gift_server_stats": L.ServerStats}
 
 
 def c_layouts(tmp_path):
@@ -152,3 +154,36 @@ def test_batch_arguments_rejected_without_device_work():
     info = L.BatchInfo()
     assert lib.gift_batch_get_info(None, C.byref(info)) == L.GIFT_EINVAL
     assert lib.gift_batch_destroy(None) == L.GIFT_OK
+
+
+def test_server_arguments_rejected_without_device_work():
+    lib = L.lib()
+    out = C.c_void_p()
+    assert lib.gift_server_create(None, C.byref(out)) == L.GIFT_EINVAL
+    terms = (L.Term * 1)()
+    terms[0].sigma, terms[0].order, terms[0].alpha = 4.0, 2, 1.0
+    good = dict(hbm_budget_bytes=1 << 30, max_inflight=4, num_streams=2, num_builders=1,
+                max_batch=8, max_batch_rows=1 << 20, storage=0, weight_model=0,
+                star_threshold=16, num_cols=2, in_dtype=0, out_dtype=0, num_terms=1,
+                terms=C.addressof(terms))
+    for field, bad in [("hbm_budget_bytes", 1000), ("max_inflight", 0), ("num_streams", 17),
+                       ("num_builders", 0), ("max_batch", 0), ("max_batch_rows", 0),
+                       ("storage", 9), ("weight_model", 3), ("star_threshold", -1),
+                       ("num_cols", 0), ("num_terms", 0), ("terms", None)]:
+        cfg = L.ServerConfig(**good)
+        setattr(cfg, field, bad)
+        assert lib.gift_server_create(C.byref(cfg), C.byref(out)) == L.GIFT_EINVAL, field
+        assert out.value is None
+    cfg = L.ServerConfig(**good)
+    cfg.in_dtype = 2
+    assert lib.gift_server_create(C.byref(cfg), C.byref(out)) == L.GIFT_EUNSUPPORTED
+    terms[0].order = 0
+    cfg = L.ServerConfig(**good)
+    assert lib.gift_server_create(C.byref(cfg), C.byref(out)) == L.GIFT_EINVAL
+    r = L.Request()
+    t = C.c_uint64()
+    assert lib.gift_server_submit(None, C.byref(r), C.byref(t)) == L.GIFT_EINVAL
+    assert lib.gift_server_wait(None, 1, 0.0, None) == L.GIFT_EINVAL
+    st = L.ServerStats()
+    assert lib.gift_server_get_stats(None, 0, C.byref(st)) == L.GIFT_EINVAL
+    assert lib.gift_server_destroy(None) == L.GIFT_OK

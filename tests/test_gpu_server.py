@@ -1,0 +1,161 @@
+"""The request-serving engine (needs a GPU): results are the same alone and in
+the mix, graphs stay resident, admission respects the memory budget, and
+failures stay with their request."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2502_17632_amd import workload as W
+
+from parity import assert_close, log
+
+pytestmark = pytest.mark.gpu
+
+EQ4 = ([4.0] * 4, [1, 2, 4, 8], [0.25] * 4)
+SIZES = [2_000, 15_000, 700, 40_000, 6_000, 25_000, 400_000]
+
+
+@pytest.fixture(scope="module")
+def pool():
+    nls = [W.sized(n, seed=3000 + i) for i, n in enumerate(SIZES)]
+    xs = [W.make_signal(nl, seed=3000 + i) for i, nl in enumerate(nls)]
+    return nls, xs
+
+
+def alone(nls, xs):
+    """Every design filtered alone by the per-design path."""
+    import torch
+    import paper_2502_17632_amd as gift
+    out = []
+    for nl, x in zip(nls, xs):
+        g = gift.build_graph(nl.num_cells, nl.net_ptr, nl.pin_cell, star_threshold=16,
+                             sigmas=[4.0])
+        out.append(gift.filter_placement(g, *EQ4, torch.tensor(x, dtype=torch.float32,
+                                                              device="cuda")))
+        torch.cuda.synchronize()
+        g.close()
+    return out
+
+
+def test_results_are_the_same_alone_and_in_the_mix(pool):
+    import torch
+    import paper_2502_17632_amd as gift
+    nls, xs = pool
+    ref = alone(nls, xs)
+    srv = gift.Server(*EQ4, num_cols=2, num_streams=3, max_batch=8)
+    rng = np.random.default_rng(7)
+    order = rng.integers(0, len(nls), size=40)
+    xt = [torch.tensor(x, dtype=torch.float32, device="cuda") for x in xs]
+    torch.cuda.synchronize()
+    tickets = []
+    for i in order:
+        nl = nls[i]
+        t, y = srv.submit(100 + int(i), nl.num_cells, nl.net_ptr, nl.pin_cell, xt[i])
+        tickets.append((t, y, int(i)))
+    built = 0
+    for t, y, i in tickets:
+        res = srv.wait(t)
+        built += res["built"]
+        assert res["status"] == 0
+        assert torch.equal(y, ref[i]), f"request for design {i} differs from the design alone"
+    st = srv.stats()
+    log(f"[server] {st['completed']} requests, {st['batches']} launches, "
+        f"{st['batched_requests']} batched, builds {st['builds']}, p50 {st['p50_ms']:.2f} ms, "
+        f"p99 {st['p99_ms']:.2f} ms")
+    assert st["completed"] == len(order) and st["failed"] == 0
+    assert st["builds"] == len(set(order.tolist())) == built
+    assert st["resident_graphs"] == len(set(order.tolist()))
+    assert st["batches"] < len(order), "no request shared a launch"
+    srv.close()
+
+
+def test_results_match_the_oracle(pool):
+    import torch
+    import paper_2502_17632_amd as gift
+    nls, xs = pool
+    srv = gift.Server(*EQ4, num_cols=2, in_dtype=torch.float64)
+    subs = []
+    # (the oracle runs on the small designs only)
+    for i in (0, 2, 4):
+        nl = nls[i]
+        fixed = torch.tensor(nl.fixed, dtype=torch.uint8, device="cuda") if i == 2 else None
+        big = torch.full((nl.num_cells, 5), -3.0, dtype=torch.float32, device="cuda")
+        t, _ = srv.submit(i, nl.num_cells, nl.net_ptr, nl.pin_cell,
+                          torch.tensor(xs[i], device="cuda"), out=big[:, 2:4], fixed=fixed)
+        subs.append((t, big, i))
+    for t, big, i in subs:
+        srv.wait(t)
+        b = big.cpu().numpy()
+        assert np.all(b[:, :2] == -3.0) and np.all(b[:, 4] == -3.0)
+        og = O.build_netlist(nls[i], star_threshold=16)
+        ref = og.filter(xs[i], *EQ4, fixed=nls[i].fixed if i == 2 else None)
+        assert_close(b[:, 2:4].astype(np.float64), ref, "f32", f"server design {i}")
+    srv.close()
+
+
+def test_budget_evicts_unused_graphs_and_results_stay_exact():
+    import torch
+    import paper_2502_17632_amd as gift
+    nls = [W.sized(20_000, seed=4000 + i) for i in range(16)]
+    xs = [W.make_signal(nl, seed=4000 + i) for i, nl in enumerate(nls)]
+    ref = alone(nls, xs)
+    xt = [torch.tensor(x, dtype=torch.float32, device="cuda") for x in xs]
+    # what one request needs (graph build bound + work) and what all the
+    # graphs take once resident, measured with an unconstrained server
+    probe = gift.Server(*EQ4, num_cols=2, max_inflight=1)
+    t, _ = probe.submit(0, nls[0].num_cells, nls[0].net_ptr, nls[0].pin_cell, xt[0])
+    probe.wait(t)
+    one = probe.stats()["peak_reserved_bytes"]
+    for i in range(1, len(nls)):
+        t, _ = probe.submit(i, nls[i].num_cells, nls[i].net_ptr, nls[i].pin_cell, xt[i])
+        probe.wait(t)
+    total = probe.stats()["resident_bytes"]
+    probe.close()
+    budget = int(max(1.3 * one, 0.6 * total))
+    log(f"[server] one request needs {one / 2**20:.1f} MiB, {len(nls)} graphs "
+        f"{total / 2**20:.1f} MiB, "
+        f"budget {budget / 2**20:.1f} MiB")
+    assert budget < total
+    srv = gift.Server(*EQ4, num_cols=2, hbm_budget_bytes=budget, max_inflight=3, max_batch=2)
+    tickets = []
+    perm = np.random.default_rng(11).permutation(len(nls))
+    for rep in range(3):
+        for i in perm:
+            nl = nls[i]
+            t, y = srv.submit(i, nl.num_cells, nl.net_ptr, nl.pin_cell, xt[i])
+            tickets.append((t, y, i))
+    for t, y, i in tickets:
+        srv.wait(t)
+        assert torch.equal(y, ref[i])
+    st = srv.stats()
+    log(f"[server] builds {st['builds']}, evictions {st['evictions']}, "
+        f"peak reserved {st['peak_reserved_bytes'] / 2**20:.1f} MiB")
+    assert st["evictions"] > 0 and st["builds"] > len(nls)
+    assert st["peak_reserved_bytes"] <= budget
+    srv.close()
+
+
+def test_failures_stay_with_their_request(pool):
+    import torch
+    import paper_2502_17632_amd as gift
+    nls, xs = pool
+    srv = gift.Server(*EQ4, num_cols=2)
+    bad_pins = nls[0].pin_cell.copy()
+    bad_pins[5] = nls[0].num_cells + 10  # out of range
+    x0 = torch.tensor(xs[0], dtype=torch.float32, device="cuda")
+    t_bad, _ = srv.submit(1, nls[0].num_cells, nls[0].net_ptr, bad_pins, x0)
+    t_ok, y = srv.submit(2, nls[0].num_cells, nls[0].net_ptr, nls[0].pin_cell, x0)
+    with pytest.raises(gift.GiftError) as e:
+        srv.wait(t_bad)
+    assert e.value.status == 1
+    assert srv.wait(t_ok)["status"] == 0
+    ref = alone(nls[:1], xs[:1])[0]
+    assert torch.equal(y, ref)
+    tiny = gift.Server(*EQ4, num_cols=2, hbm_budget_bytes=2 << 20)
+    t, _ = tiny.submit(3, nls[3].num_cells, nls[3].net_ptr, nls[3].pin_cell,
+                       torch.tensor(xs[3], dtype=torch.float32, device="cuda"))
+    with pytest.raises(gift.GiftError) as e:
+        tiny.wait(t)
+    assert e.value.status == 2
+    tiny.close()
+    srv.close()
