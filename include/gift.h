@@ -192,6 +192,12 @@ gift_status gift_graph_add_sigma(gift_graph *graph, double sigma, void *stream);
 
 gift_status gift_graph_get_info(const gift_graph *graph, gift_graph_info *info);
 
+/* Row-tile schedule gift_filter_placement uses for this graph: 0 (default:
+ * tiles of up to 2048 entries / 512 rows, rows longer than 256 entries
+ * alone) or 1 (1024 / 256, 128).  Both give results within rounding of each
+ * other; the choice only changes speed (and the order of float32 sums). */
+gift_status gift_graph_set_tile_class(gift_graph *graph, int32_t tile_class);
+
 /*
  * Copy the graph to host memory (for inspection and tests).  Any pointer may
  * be NULL.  row_ptr: int64[R+1]; col: int32[nnz]; w: double[nnz] (A's

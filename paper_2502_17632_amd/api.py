@@ -62,6 +62,10 @@ class Graph:
         L.check(L.lib().gift_graph_get_info(self._h, C.byref(inf)), "gift_graph_get_info")
         return {k: getattr(inf, k) for k, _ in L.GraphInfo._fields_}
 
+    def set_tile_class(self, tile_class: int):
+        L.check(L.lib().gift_graph_set_tile_class(self._h, int(tile_class)),
+                "gift_graph_set_tile_class")
+
     def add_sigma(self, sigma: float, stream=None):
         L.check(L.lib().gift_graph_add_sigma(self._h, float(sigma), _stream_handle(stream)),
                 "gift_graph_add_sigma")

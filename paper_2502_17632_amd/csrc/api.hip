@@ -206,6 +206,15 @@ gift_status gift_graph_get_info(const gift_graph *g, gift_graph_info *info) {
   return GIFT_OK;
 }
 
+gift_status gift_graph_set_tile_class(gift_graph *g, int32_t tile_class) {
+  clear_error();
+  if (!g) return set_error(GIFT_EINVAL, "gift_graph_set_tile_class: NULL graph");
+  if (tile_class < 0 || tile_class >= kTileClasses)
+    return set_error(GIFT_EINVAL, "tile_class %d not in [0, %d)", tile_class, kTileClasses);
+  g->tile_class = tile_class;
+  return GIFT_OK;
+}
+
 gift_status gift_graph_export(const gift_graph *g, int64_t *row_ptr, int32_t *col, double *w,
                               double *deg, void *stream) {
   clear_error();

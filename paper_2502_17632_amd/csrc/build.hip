@@ -16,9 +16,10 @@
 //      each pin among the net's first occurrences); long nets by a block-wide
 //      bitonic sort in LDS or a merge sort through global memory
 //   2. per net: clique or star, virtual id, weight
-//   3. per cell row: number of directed entries (atomic histogram over pins),
-//      exclusive scan -> row slices; emit (col, net) keys into each row's
-//      slice (atomic slot reservation per pin: arbitrary order in a slice)
+//   3. per cell row: number of directed entries (atomic histogram over pins;
+//      the atomic's old value is the pin's slice within the row), exclusive
+//      scan -> row slices; emit each pin's (col, net) keys into its slice
+//      (arbitrary order of the slices within a row)
 //   4. per row tile, in LDS: sort each row's keys by (col, net) (rank among
 //      the row's keys, which are distinct), count distinct columns.  The
 //      sorted order fixes every summation order below, so the result does
@@ -252,7 +253,11 @@ struct EmitArgs {
   int64_t E, P, N;
 };
 
-__global__ void k_count(EmitArgs a, int32_t *cnt) {
+// Counts the entries of every cell row and reserves each pin's slice in its
+// row at the same time: the atomic returns the slice's start within the row
+// (arbitrary order among the row's pins; the row sort makes the result
+// independent of it).
+__global__ void k_count(EmitArgs a, int32_t *cnt, int32_t *slot) {
   int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (p >= a.P) return;
   int64_t e = a.pin_net[p];
@@ -262,31 +267,60 @@ __global__ void k_count(EmitArgs a, int32_t *cnt) {
   if (m < 2 || i < 0 || i >= m) return;
   int32_t c = a.ucell[p];
   if (c < 0 || c >= a.N) return;
-  atomicAdd(&cnt[c], a.is_star[e] ? 1 : static_cast<int32_t>(m - 1));
+  slot[p] = atomicAdd(&cnt[c], a.is_star[e] ? 1 : static_cast<int32_t>(m - 1));
 }
 
-__global__ void k_emit(EmitArgs a, const int64_t *zoff, int32_t *cursor, uint64_t *zkey) {
-  int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (p >= a.P) return;
-  int64_t e = a.pin_net[p];
-  int64_t lo = a.net_ptr[e];
-  int64_t i = p - lo;
-  int64_t m = a.M[e];
-  if (m < 2 || i >= m) return;
-  int32_t c = a.ucell[p];
-  const uint64_t net = static_cast<uint64_t>(e);
-  if (a.is_star[e]) {
-    int32_t slot = atomicAdd(&cursor[c], 1);
-    uint64_t v = static_cast<uint64_t>(a.N + a.vrank[e]);
-    zkey[zoff[c] + slot] = (v << 32) | net;
-  } else {
-    int32_t slot = atomicAdd(&cursor[c], static_cast<int32_t>(m - 1));
-    uint64_t *dst = zkey + zoff[c] + slot;
-    for (int64_t j = 0; j < m; ++j) {
-      if (j == i) continue;
-      uint64_t b = static_cast<uint32_t>(a.ucell[lo + j]);
-      *dst++ = (b << 32) | net;
+// Writes each pin's (col, net) keys into the slice k_count reserved.  The
+// block's 256 pins first publish their slices in LDS (start, length, net,
+// position in the net); then the block's threads take the keys one each,
+// in slice order, so consecutive threads write consecutive addresses of a
+// slice instead of every thread looping over its own slice.
+__global__ __launch_bounds__(kBlock) void k_emit(EmitArgs a, const int64_t *zoff,
+                                                 const int32_t *slot, uint64_t *zkey) {
+  __shared__ int32_t first[kBlock + 1];  // exclusive prefix of the keys per pin
+  __shared__ int64_t dst[kBlock];        // first key of the pin's slice in zkey
+  __shared__ int64_t lo_of[kBlock];      // first pin of the pin's net
+  __shared__ int64_t net_of[kBlock];
+  __shared__ int32_t self_of[kBlock];    // the pin's index in its net; -1: star
+  __shared__ int32_t tmp[kBlock / kWave];
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  int32_t n = 0;
+  if (p < a.P) {
+    const int64_t e = a.pin_net[p];
+    const int64_t lo = a.net_ptr[e];
+    const int64_t i = p - lo;
+    const int64_t m = a.M[e];
+    if (m >= 2 && i < m) {
+      const bool star = a.is_star[e] != 0;
+      n = star ? 1 : static_cast<int32_t>(m - 1);
+      dst[threadIdx.x] = zoff[a.ucell[p]] + slot[p];
+      lo_of[threadIdx.x] = star ? a.N + a.vrank[e] : lo;
+      net_of[threadIdx.x] = e;
+      self_of[threadIdx.x] = star ? -1 : static_cast<int32_t>(i);
     }
+  }
+  int32_t total = 0;
+  first[threadIdx.x] = block_excl_scan<int32_t>(n, &total, tmp);
+  if (threadIdx.x == 0) first[kBlock] = total;
+  __syncthreads();
+  for (int32_t q = threadIdx.x; q < total; q += kBlock) {
+    int lo = 0, hi = kBlock;  // last pin t with first[t] <= q
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (first[mid] <= q) lo = mid;
+      else hi = mid;
+    }
+    const int t = lo;
+    const int32_t idx = q - first[t];
+    const uint64_t net = static_cast<uint64_t>(net_of[t]);
+    uint64_t col;
+    if (self_of[t] < 0) {
+      col = static_cast<uint64_t>(lo_of[t]);  // the star's virtual node
+    } else {
+      const int32_t j = idx + (idx >= self_of[t] ? 1 : 0);
+      col = static_cast<uint32_t>(a.ucell[lo_of[t] + j]);
+    }
+    zkey[dst[t] + idx] = (col << 32) | net;
   }
 }
 
@@ -759,15 +793,16 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
   GIFT_TRY(check_launch("k_virtual_map"));
 
   // 3. entries per cell row, row tiles over the pre-merge slices
-  int32_t *cnt = nullptr, *row_tiles = nullptr;
+  int32_t *cnt = nullptr, *row_tiles = nullptr, *slot = nullptr;
   int64_t *zoff = nullptr, *row_tile_counts = nullptr;
   GIFT_TRY(sc.get(&cnt, N, "row counts"));
+  GIFT_TRY(sc.get(&slot, P, "pin slices"));
   GIFT_TRY(sc.get(&zoff, N + 1, "row offsets"));
   GIFT_TRY(sc.get(&row_tiles, N + 2, "row tiles"));
   GIFT_TRY(sc.get(&row_tile_counts, 2, "row tile counts"));
   GIFT_HIP(hipMemsetAsync(cnt, 0, N * 4 + 4, st));
   EmitArgs ea{net_ptr, ucell, pin_net, M, is_star, vrank, E, P, N};
-  k_count<<<grid_for(P), kBlock, 0, st>>>(ea, cnt);
+  k_count<<<grid_for(P), kBlock, 0, st>>>(ea, cnt, slot);
   GIFT_TRY(check_launch("k_count"));
   GIFT_TRY(scan_i32_to_i64(cnt, zoff, N, st));
   GIFT_TRY(build_tiles64(zoff, N, N, kBuildTiles, st, row_tiles, row_tile_counts));
@@ -790,13 +825,11 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
 
   // 3b. emit
   uint64_t *zkey = nullptr, *zsort = nullptr;
-  int32_t *cursor = nullptr, *ucnt = nullptr;
+  int32_t *ucnt = nullptr;
   GIFT_TRY(sc.get(&zkey, Z, "emitted keys"));
   GIFT_TRY(sc.get(&zsort, Z, "sorted keys"));
-  GIFT_TRY(sc.get(&cursor, N, "row cursors"));
   GIFT_TRY(sc.get(&ucnt, R, "distinct counts"));
-  GIFT_HIP(hipMemsetAsync(cursor, 0, N * 4 + 4, st));
-  k_emit<<<grid_for(P), kBlock, 0, st>>>(ea, zoff, cursor, zkey);
+  k_emit<<<grid_for(P), kBlock, 0, st>>>(ea, zoff, slot, zkey);
   GIFT_TRY(check_launch("k_emit"));
 
   // 4. sort rows

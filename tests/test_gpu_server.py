@@ -130,7 +130,9 @@ def test_budget_evicts_unused_graphs_and_results_stay_exact():
     st = srv.stats()
     log(f"[server] builds {st['builds']}, evictions {st['evictions']}, "
         f"peak reserved {st['peak_reserved_bytes'] / 2**20:.1f} MiB")
-    assert st["evictions"] > 0 and st["builds"] > len(nls)
+    # every graph was built at least once and some were evicted to stay in
+    # budget (requests for one design admitted together share one build)
+    assert st["evictions"] > 0 and st["builds"] >= len(nls)
     assert st["peak_reserved_bytes"] <= budget
     srv.close()
 
