@@ -30,6 +30,7 @@
 //      col; star rows copy the net's sorted cells with weight M w(M)
 //   7. per sigma: s_i = 1/sqrt(d_i + sigma), a_ij = (w_ij s_i) s_j,
 //      diag_i = (sigma s_i) s_i
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -64,8 +65,38 @@ __device__ __forceinline__ double star_weight(int64_t m, int model) {
                                     : static_cast<double>(m) / static_cast<double>(m - 1);
 }
 
-__device__ __forceinline__ uint32_t key_col(uint64_t k) { return static_cast<uint32_t>(k >> 32); }
-__device__ __forceinline__ uint32_t key_net(uint64_t k) { return static_cast<uint32_t>(k); }
+// An emitted entry is one 64-bit key: its column in the high bits, the net
+// in the middle and, when the three fit, the net's distinct cell count M in
+// the low bits (the merge then derives the weight from M instead of reading
+// it per net).  Sorting keys sorts by (column, net): a row never holds two
+// keys of one (column, net).
+struct KeyLayout {
+  int32_t col_shift;  // column = key >> col_shift
+  int32_t net_shift;  // net = (key >> net_shift) & net_mask
+  uint64_t net_mask;
+  uint64_t m_mask;    // M = key & m_mask; 0 when M is not in the key
+};
+__device__ __forceinline__ uint32_t key_col(uint64_t k, const KeyLayout &L) {
+  return static_cast<uint32_t>(k >> L.col_shift);
+}
+__device__ __forceinline__ uint32_t key_net(uint64_t k, const KeyLayout &L) {
+  return static_cast<uint32_t>((k >> L.net_shift) & L.net_mask);
+}
+
+int bits_for(int64_t v) {  // bits to hold 0..v
+  int b = 1;
+  while (b < 63 && (int64_t(1) << b) <= v) ++b;
+  return b;
+}
+
+// The widest layout that fits: M packed when bits(max column) + bits(max
+// net) + bits(max M) <= 64, else column and net in 32 bits each.
+KeyLayout key_layout(int64_t max_col, int64_t max_net, int64_t max_m) {
+  const int cb = bits_for(max_col), nb = bits_for(max_net), mb = bits_for(max_m);
+  if (cb + nb + mb <= 64)
+    return KeyLayout{nb + mb, mb, (uint64_t(1) << nb) - 1, (uint64_t(1) << mb) - 1};
+  return KeyLayout{32, 0, 0xffffffffull, 0};
+}
 
 // Fills seg[i] = k for every entry i of segment k (segments given by
 // local offsets loff[0..ns]); one thread per segment.
@@ -77,12 +108,13 @@ __device__ __forceinline__ void fill_segment_ids(const int32_t *loff, int ns, ui
 // ---------------------------------------------------------------------------
 // 0. netlist checks
 // ---------------------------------------------------------------------------
-__global__ void k_check_netptr(const int64_t *net_ptr, int64_t E, int64_t P, uint32_t *flag) {
+// net_ptr must start at 0 and not decrease (so it ends at the pin count,
+// which is read back with this flag).
+__global__ void k_check_netptr(const int64_t *net_ptr, int64_t E, uint32_t *flag) {
   int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e > E) return;
   const int64_t v = net_ptr[e];
-  bool bad = v < 0 || v > P || (e == 0 && v != 0) || (e == E && v != P) ||
-             (e < E && net_ptr[e + 1] < v);
+  bool bad = v < 0 || (e == 0 && v != 0) || (e < E && net_ptr[e + 1] < v);
   if (bad) atomicOr(flag, kFlagBadNetPtr);
 }
 
@@ -227,14 +259,45 @@ __global__ __launch_bounds__(kBlock) void k_net_tiles(NetArgs a) {
 // ---------------------------------------------------------------------------
 // 2. classify nets
 // ---------------------------------------------------------------------------
-__global__ void k_classify(const int32_t *M, int64_t E, int64_t T, int model,
-                           int32_t *is_star, double *wnet) {
+// Per net: star or clique, weight; and the largest net size of the block
+// into bmax[blockIdx.x].
+__global__ __launch_bounds__(kBlock) void k_classify(const int32_t *M, int64_t E, int64_t T,
+                                                     int model, int32_t *is_star, double *wnet,
+                                                     int32_t *bmax) {
+  __shared__ int32_t red[kBlock];
   int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e >= E) return;
-  int64_t m = M[e];
-  bool star = m >= 2 && T > 0 && m > T;
-  is_star[e] = star ? 1 : 0;
-  wnet[e] = m < 2 ? 0.0 : (star ? star_weight(m, model) : clique_weight(m, model));
+  int32_t mine = 0;
+  if (e < E) {
+    int64_t m = M[e];
+    bool star = m >= 2 && T > 0 && m > T;
+    is_star[e] = star ? 1 : 0;
+    wnet[e] = m < 2 ? 0.0 : (star ? star_weight(m, model) : clique_weight(m, model));
+    mine = static_cast<int32_t>(m);
+  }
+  red[threadIdx.x] = mine;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off && red[threadIdx.x + off] > red[threadIdx.x])
+      red[threadIdx.x] = red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bmax[blockIdx.x] = red[0];
+}
+
+// *out = max of v[0..n), one block.
+__global__ __launch_bounds__(kBlock) void k_max_reduce(const int32_t *v, int64_t n,
+                                                       int64_t *out) {
+  __shared__ int32_t red[kBlock];
+  int32_t m = 0;
+  for (int64_t i = threadIdx.x; i < n; i += kBlock) m = v[i] > m ? v[i] : m;
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off && red[threadIdx.x + off] > red[threadIdx.x])
+      red[threadIdx.x] = red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
 }
 
 __global__ void k_virtual_map(const int32_t *is_star, const int64_t *vrank, int64_t E,
@@ -251,6 +314,7 @@ struct EmitArgs {
   const int32_t *ucell, *pin_net, *M, *is_star;
   const int64_t *vrank;
   int64_t E, P, N;
+  KeyLayout L;
 };
 
 // Counts the entries of every cell row and reserves each pin's slice in its
@@ -282,6 +346,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(EmitArgs a, const int64_t *zoff
   __shared__ int64_t lo_of[kBlock];      // first pin of the pin's net
   __shared__ int64_t net_of[kBlock];
   __shared__ int32_t self_of[kBlock];    // the pin's index in its net; -1: star
+  __shared__ int32_t m_of[kBlock];
   __shared__ int32_t tmp[kBlock / kWave];
   const int64_t p = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
   int32_t n = 0;
@@ -297,6 +362,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(EmitArgs a, const int64_t *zoff
       lo_of[threadIdx.x] = star ? a.N + a.vrank[e] : lo;
       net_of[threadIdx.x] = e;
       self_of[threadIdx.x] = star ? -1 : static_cast<int32_t>(i);
+      m_of[threadIdx.x] = static_cast<int32_t>(m);
     }
   }
   int32_t total = 0;
@@ -312,7 +378,8 @@ __global__ __launch_bounds__(kBlock) void k_emit(EmitArgs a, const int64_t *zoff
     }
     const int t = lo;
     const int32_t idx = q - first[t];
-    const uint64_t net = static_cast<uint64_t>(net_of[t]);
+    const uint64_t tail = (static_cast<uint64_t>(net_of[t]) << a.L.net_shift) |
+                          (a.L.m_mask ? static_cast<uint64_t>(m_of[t]) : 0);
     uint64_t col;
     if (self_of[t] < 0) {
       col = static_cast<uint64_t>(lo_of[t]);  // the star's virtual node
@@ -320,7 +387,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(EmitArgs a, const int64_t *zoff
       const int32_t j = idx + (idx >= self_of[t] ? 1 : 0);
       col = static_cast<uint32_t>(a.ucell[lo_of[t] + j]);
     }
-    zkey[dst[t] + idx] = (col << 32) | net;
+    zkey[dst[t] + idx] = (col << a.L.col_shift) | tail;
   }
 }
 
@@ -333,12 +400,14 @@ struct RowArgs {
   uint64_t *zsort;  // sorted keys
   int32_t *ucnt;    // distinct columns per row
   const int32_t *tiles;
+  KeyLayout L;
 };
 
-__device__ int32_t count_heads_block(const uint64_t *k, int64_t n, int32_t *tmp) {
+__device__ int32_t count_heads_block(const uint64_t *k, int64_t n, int32_t *tmp,
+                                     const KeyLayout &L) {
   int32_t heads = 0;
   for (int64_t i = threadIdx.x; i < n; i += kBlock)
-    if (i == 0 || key_col(k[i]) != key_col(k[i - 1])) ++heads;
+    if (i == 0 || key_col(k[i], L) != key_col(k[i - 1], L)) ++heads;
   return block_sum<int32_t>(heads, tmp);
 }
 
@@ -364,14 +433,14 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_tiles(RowArgs a) {
       __syncthreads();
       lds_bitonic_sort<uint64_t>(keys, np);
       for (int i = threadIdx.x; i < n64; i += kBlock) a.zsort[z0 + i] = keys[i];
-      total = count_heads_block(keys, n64, tmp);
+      total = count_heads_block(keys, n64, tmp, a.L);
     } else {
       uint64_t *ka = a.zkey + z0, *kb = a.zsort + z0;
       if (!block_merge_sort_global<uint64_t, kChunk64>(ka, kb, n64, keys, ~0ull)) {
         for (int64_t i = threadIdx.x; i < n64; i += kBlock) kb[i] = ka[i];
         __syncthreads();
       }
-      total = count_heads_block(kb, n64, tmp);
+      total = count_heads_block(kb, n64, tmp, a.L);
     }
     if (threadIdx.x == 0) a.ucnt[r0] = total;
     return;
@@ -391,14 +460,14 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_tiles(RowArgs a) {
   for (int i = threadIdx.x; i < n; i += kBlock) {
     const int k = seg[i];
     const uint64_t me = key[i];
-    const uint32_t mc = key_col(me);
+    const uint32_t mc = key_col(me, a.L);
     int rank = 0;
     uint8_t h = 1;
     for (int j = loff[k]; j < loff[k + 1]; ++j) {
       const uint64_t o = key[j];
       if (o < me) {
         ++rank;
-        if (key_col(o) == mc) h = 0;
+        if (key_col(o, a.L) == mc) h = 0;
       }
     }
     a.zsort[z0 + loff[k] + rank] = me;
@@ -437,15 +506,29 @@ struct MergeArgs {
   int32_t *col;
   double *w;
   double *deg;
+  KeyLayout L;
+  int64_t N;
+  int32_t model;
 };
+
+// Weight one key adds: from the M packed in the key (a column >= N is a star
+// node: weight M w(M)), else the net's weight.
+__device__ __forceinline__ double key_weight(uint64_t k, const MergeArgs &a) {
+  if (a.L.m_mask) {
+    const int64_t m = static_cast<int64_t>(k & a.L.m_mask);
+    return static_cast<int64_t>(key_col(k, a.L)) >= a.N ? star_weight(m, a.model)
+                                                        : clique_weight(m, a.model);
+  }
+  return a.wnet[key_net(k, a.L)];
+}
 
 // Weight of the run of equal columns starting at sorted entry i (ascending
 // net id), reading the keys from `k` (length n).
 __device__ __forceinline__ double run_weight(const uint64_t *k, int64_t i, int64_t n,
-                                             const double *wnet) {
-  const uint32_t c = key_col(k[i]);
-  double s = wnet[key_net(k[i])];
-  for (int64_t j = i + 1; j < n && key_col(k[j]) == c; ++j) s = s + wnet[key_net(k[j])];
+                                             const MergeArgs &a) {
+  const uint32_t c = key_col(k[i], a.L);
+  double s = key_weight(k[i], a);
+  for (int64_t j = i + 1; j < n && key_col(k[j], a.L) == c; ++j) s = s + key_weight(k[j], a);
   return s;
 }
 
@@ -468,12 +551,13 @@ __global__ __launch_bounds__(kBlock) void k_row_merge_tiles(MergeArgs a) {
     int64_t base = 0;
     for (int64_t c0 = 0; c0 < n64; c0 += kBlock) {
       const int64_t i = c0 + threadIdx.x;
-      const int f = (i < n64 && (i == 0 || key_col(k[i]) != key_col(k[i - 1]))) ? 1 : 0;
+      const int f =
+          (i < n64 && (i == 0 || key_col(k[i], a.L) != key_col(k[i - 1], a.L))) ? 1 : 0;
       int32_t total;
       const int32_t pos = block_excl_scan<int32_t>(f, &total, tmp);
       if (f) {
-        a.col[o0 + base + pos] = static_cast<int32_t>(key_col(k[i]));
-        a.w[o0 + base + pos] = run_weight(k, i, n64, a.wnet);
+        a.col[o0 + base + pos] = static_cast<int32_t>(key_col(k[i], a.L));
+        a.w[o0 + base + pos] = run_weight(k, i, n64, a);
       }
       base += total;
     }
@@ -512,16 +596,16 @@ __global__ __launch_bounds__(kBlock) void k_row_merge_tiles(MergeArgs a) {
   const int b = threadIdx.x * kPer;
   int mine = 0;
   for (int i = b; i < b + kPer && i < n; ++i)
-    mine += (i == loff[seg[i]] || key_col(key[i]) != key_col(key[i - 1])) ? 1 : 0;
+    mine += (i == loff[seg[i]] || key_col(key[i], a.L) != key_col(key[i - 1], a.L)) ? 1 : 0;
   int32_t total;
   int32_t pos = block_excl_scan<int32_t>(mine, &total, tmp);
   for (int i = b; i < b + kPer && i < n; ++i) {
     const int k = seg[i];
     const int end = loff[k + 1];
-    if (i == loff[k] || key_col(key[i]) != key_col(key[i - 1])) {
-      const uint32_t c = key_col(key[i]);
-      double s = a.wnet[key_net(key[i])];
-      for (int j = i + 1; j < end && key_col(key[j]) == c; ++j) s = s + a.wnet[key_net(key[j])];
+    if (i == loff[k] || key_col(key[i], a.L) != key_col(key[i - 1], a.L)) {
+      const uint32_t c = key_col(key[i], a.L);
+      double s = key_weight(key[i], a);
+      for (int j = i + 1; j < end && key_col(key[j], a.L) == c; ++j) s = s + key_weight(key[j], a);
       a.col[o0 + pos] = static_cast<int32_t>(c);
       a.w[o0 + pos] = s;
       mw[pos] = s;
@@ -725,14 +809,10 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
     if (P) GIFT_HIP(hipMemcpyAsync(dp, d->pin_cell, P * 4, hipMemcpyHostToDevice, st));
     net_ptr = dn;
     pin = dp;
-  } else {
-    GIFT_HIP(hipMemcpyAsync(&P, d->net_ptr + E, 8, hipMemcpyDeviceToHost, st));
-    GIFT_HIP(hipStreamSynchronize(st));
-    if (P < 0) return set_error(GIFT_EINVAL, "net_ptr[num_nets] is negative");
   }
-  if (P >= (int64_t(1) << 31) || N + E >= (int64_t(1) << 31))
-    return set_error(GIFT_EUNSUPPORTED, "netlist too large (pins %lld, cells+nets %lld)",
-                     (long long)P, (long long)(N + E));
+  if (N + E >= (int64_t(1) << 31))
+    return set_error(GIFT_EUNSUPPORTED, "netlist too large (cells+nets %lld)",
+                     (long long)(N + E));
 
   uint32_t *flag = nullptr;
   int64_t *flag64 = nullptr;
@@ -740,28 +820,29 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
   GIFT_TRY(sc.get(&flag64, 1, "flag copy"));
   GIFT_HIP(hipMemsetAsync(flag, 0, 4, st));
 
-  // 0. check net_ptr (read back before anything trusts it), tile the nets
-  k_check_netptr<<<grid_for(E + 1), kBlock, 0, st>>>(net_ptr, E, P, flag);
+  // 0. check net_ptr and tile the nets, then read the flag, the pin count
+  //    and the tile count back together; nothing reads pins before the check
+  //    passed (tiling reads net_ptr only and stays in bounds for any values)
+  k_check_netptr<<<grid_for(E + 1), kBlock, 0, st>>>(net_ptr, E, flag);
   GIFT_TRY(check_launch("k_check_netptr"));
   k_flag_to_i64<<<1, 1, 0, st>>>(flag, flag64);
   GIFT_TRY(check_launch("k_flag_to_i64"));
-  int64_t h0 = 0;
-  {
-    const int64_t *ptrs[1] = {flag64};
-    GIFT_TRY(read_scalars(sc, st, ptrs, 1, &h0));
-  }
-  if (h0 & kFlagBadNetPtr)
-    return set_error(GIFT_EINVAL, "net_ptr must start at 0, end at the pin count and not decrease");
   int32_t *net_tiles = nullptr;
   int64_t *net_tile_counts = nullptr;
   GIFT_TRY(sc.get(&net_tiles, E + 2, "net tiles"));
   GIFT_TRY(sc.get(&net_tile_counts, 2, "net tile counts"));
   GIFT_TRY(build_tiles64(net_ptr, E, E, kBuildTiles, st, net_tiles, net_tile_counts));
-  int64_t num_net_tiles = 0;
+  int64_t h0[3] = {0, 0, 0};
   {
-    const int64_t *ptrs[1] = {net_tile_counts};
-    GIFT_TRY(read_scalars(sc, st, ptrs, 1, &num_net_tiles));
+    const int64_t *ptrs[3] = {flag64, net_ptr + E, net_tile_counts};
+    GIFT_TRY(read_scalars(sc, st, ptrs, 3, h0));
   }
+  if (h0[0] & kFlagBadNetPtr)
+    return set_error(GIFT_EINVAL, "net_ptr must start at 0, end at the pin count and not decrease");
+  if (d->mem_space != GIFT_MEM_HOST) P = h0[1];
+  const int64_t num_net_tiles = h0[2];
+  if (P >= (int64_t(1) << 31))
+    return set_error(GIFT_EUNSUPPORTED, "netlist too large (pins %lld)", (long long)P);
 
   int32_t *M = nullptr, *ucell = nullptr, *pin_net = nullptr;
   uint32_t *tmp32 = nullptr;
@@ -785,8 +866,14 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
   GIFT_TRY(sc.get(&vrank, E + 1, "virtual ranks"));
   GIFT_TRY(sc.get(&wnet, E, "net weights"));
   GIFT_TRY(sc.get(&virt_net, E, "virtual nets"));
+  int64_t *mmax = nullptr;
+  int32_t *bmax = nullptr;
+  GIFT_TRY(sc.get(&mmax, 1, "largest net"));
+  GIFT_TRY(sc.get(&bmax, grid_for(E), "largest net per block"));
   k_classify<<<grid_for(E), kBlock, 0, st>>>(M, E, d->star_threshold, d->weight_model, is_star,
-                                             wnet);
+                                             wnet, bmax);
+  GIFT_TRY(check_launch("k_classify"));
+  k_max_reduce<<<1, kBlock, 0, st>>>(bmax, grid_for(E), mmax);
   GIFT_TRY(check_launch("k_classify"));
   GIFT_TRY(scan_i32_to_i64(is_star, vrank, E, st));
   k_virtual_map<<<grid_for(E), kBlock, 0, st>>>(is_star, vrank, E, virt_net);
@@ -801,7 +888,7 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
   GIFT_TRY(sc.get(&row_tiles, N + 2, "row tiles"));
   GIFT_TRY(sc.get(&row_tile_counts, 2, "row tile counts"));
   GIFT_HIP(hipMemsetAsync(cnt, 0, N * 4 + 4, st));
-  EmitArgs ea{net_ptr, ucell, pin_net, M, is_star, vrank, E, P, N};
+  EmitArgs ea{net_ptr, ucell, pin_net, M, is_star, vrank, E, P, N, KeyLayout{}};
   k_count<<<grid_for(P), kBlock, 0, st>>>(ea, cnt, slot);
   GIFT_TRY(check_launch("k_count"));
   GIFT_TRY(scan_i32_to_i64(cnt, zoff, N, st));
@@ -810,13 +897,15 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
   GIFT_TRY(check_launch("k_flag_to_i64"));
 
   // sizes back to the host: flag, V, Z, row tiles
-  int64_t h1[4] = {0, 0, 0, 0};
+  int64_t h1[5] = {0, 0, 0, 0, 0};
   {
-    const int64_t *ptrs[4] = {flag64, vrank + E, zoff + N, row_tile_counts};
-    GIFT_TRY(read_scalars(sc, st, ptrs, 4, h1));
+    const int64_t *ptrs[5] = {flag64, vrank + E, zoff + N, row_tile_counts, mmax};
+    GIFT_TRY(read_scalars(sc, st, ptrs, 5, h1));
   }
   if (h1[0] & kFlagBadPin) return set_error(GIFT_EINVAL, "a pin names a cell outside [0, num_cells)");
   const int64_t V = h1[1], Z = h1[2], num_row_tiles = h1[3], R = N + V;
+  const KeyLayout L = key_layout(R > 0 ? R - 1 : 0, E > 0 ? E - 1 : 0, h1[4]);
+  ea.L = L;
   if (R >= (int64_t(1) << 31))
     return set_error(GIFT_EUNSUPPORTED, "too many rows (%lld)", (long long)R);
   g->num_cells = N;
@@ -834,7 +923,7 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
 
   // 4. sort rows
   if (num_row_tiles > 0) {
-    RowArgs ra{zoff, zkey, zsort, ucnt, row_tiles};
+    RowArgs ra{zoff, zkey, zsort, ucnt, row_tiles, L};
     k_row_sort_tiles<<<static_cast<unsigned>(num_row_tiles), kBlock, 0, st>>>(ra);
     GIFT_TRY(check_launch("k_row_sort_tiles"));
   }
@@ -885,7 +974,8 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
 
   // 6. merge
   if (num_row_tiles > 0) {
-    MergeArgs ma{zoff, zsort, wnet, g->row_ptr, row_tiles, g->col, g->w, g->deg};
+    MergeArgs ma{zoff, zsort, wnet, g->row_ptr, row_tiles, g->col, g->w, g->deg,
+                 L, N, d->weight_model};
     k_row_merge_tiles<<<static_cast<unsigned>(num_row_tiles), kBlock, 0, st>>>(ma);
     GIFT_TRY(check_launch("k_row_merge_tiles"));
   }

@@ -1,6 +1,7 @@
 // Internal declarations shared by the library's HIP sources.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -51,6 +52,23 @@ class ProfScope {
   int idx_;
   hipStream_t stream_;
 };
+
+// When the profiler is on, takes a pair of events for one launch of class
+// `cls` (to be recorded by the launch itself) and returns true.
+bool prof_launch_events(int cls, double bytes, hipEvent_t *start, hipEvent_t *stop);
+
+// Launches kern<<<grid, 256>>>(args...) on `st`; when `timed` and the
+// profiler is on, the dispatch itself records the launch's start and end.
+template <typename... Args>
+gift_status launch_timed(void (*kern)(Args...), unsigned grid, hipStream_t st, bool timed,
+                         int cls, double bytes, const char *what, Args... args) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (timed && prof_launch_events(cls, bytes, &e0, &e1))
+    hipExtLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, st, e0, e1, 0, args...);
+  else
+    kern<<<grid, 256, 0, st>>>(args...);
+  return check_launch(what);
+}
 
 // ---------------------------------------------------------------------------
 // Device memory: a stream-ordered caching allocator (see api.hip).  A block

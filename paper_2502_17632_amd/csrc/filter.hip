@@ -21,7 +21,6 @@
 // shared signal buffers come from a small device table.
 #include <cmath>
 #include <cstring>
-#include <optional>
 
 #include "common.h"
 #include "devutil.h"
@@ -441,14 +440,18 @@ gift_status enqueue_chunk(const FilterPlan &pl, const ChunkBuffers &bf, int32_t 
       }
       const int64_t tiles = fin ? pl.num_final_tiles : pl.num_tiles;
       if (tiles > 0) {
-        std::optional<ProfScope> ps;
-        if (pl.profile)
-          ps.emplace(st, fin ? GIFT_PROF_SPMM_FINAL : GIFT_PROF_SPMM, pass_bytes(pl, C, fin));
         const LaunchArgs l = launch_args(pl, grp, fin);
         const unsigned grid = static_cast<unsigned>(tiles);
-        if (fin) k_spmm<D, C, true, TC, kBatch><<<grid, kBlock, 0, st>>>(l, cur, nullptr, fa);
-        else k_spmm<D, C, false, TC, kBatch><<<grid, kBlock, 0, st>>>(l, cur, dst, fa);
-        GIFT_TRY(check_launch("k_spmm"));
+        const void *x = cur;
+        void *y = dst;
+        if (fin)
+          GIFT_TRY(launch_timed(k_spmm<D, C, true, TC, kBatch>, grid, st, pl.profile,
+                                GIFT_PROF_SPMM_FINAL, pass_bytes(pl, C, true), "k_spmm", l, x,
+                                y, fa));
+        else
+          GIFT_TRY(launch_timed(k_spmm<D, C, false, TC, kBatch>, grid, st, pl.profile,
+                                GIFT_PROF_SPMM, pass_bytes(pl, C, false), "k_spmm", l, x, y,
+                                fa));
       }
       if (!fin) cur = dst;
     }

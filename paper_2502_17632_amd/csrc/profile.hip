@@ -1,6 +1,8 @@
-// Event profiler: when enabled, each timed launch is bracketed by two HIP
-// events recorded on its own stream, so benchmarks can read per-launch device
-// durations of kernels that run inside library calls.
+// Event profiler: when enabled, each timed launch gets two HIP events, so
+// benchmarks can read per-launch device durations of kernels that run inside
+// library calls.  Single kernels carry the events in their dispatch
+// (hipExtLaunchKernel: no extra packets between launches); a scope spanning
+// several launches records them on its stream around the launches.
 #include <mutex>
 
 #include "common.h"
@@ -58,6 +60,23 @@ ProfScope::~ProfScope() {
   Profiler &p = prof();
   std::lock_guard<std::mutex> lk(p.m);
   if (idx_ < static_cast<int>(p.recs.size())) (void)hipEventRecord(p.recs[idx_].b, stream_);
+}
+
+bool prof_launch_events(int cls, double bytes, hipEvent_t *start, hipEvent_t *stop) {
+  *start = *stop = nullptr;
+  Profiler &p = prof();
+  std::lock_guard<std::mutex> lk(p.m);
+  if (!p.on) return false;
+  hipEvent_t a = p.take(), b = p.take();
+  if (!a || !b) {
+    if (a) p.pool.push_back(a);
+    if (b) p.pool.push_back(b);
+    return false;
+  }
+  p.recs.push_back(Rec{a, b, cls, bytes});
+  *start = a;
+  *stop = b;
+  return true;
 }
 
 }  // namespace gift
