@@ -385,6 +385,16 @@ def main():
         torch.cuda.synchronize()
         f_ms = ev0.elapsed_time(ev1) / reps
         out["filter_only"] = {"ms": round(f_ms, 4), "nnz_cols_per_s": work / (f_ms * 1e-3)}
+        # what the filter does to the placement: smoothness / quadratic
+        # wirelength, Rayleigh quotient and HPWL before and after
+        t0 = time.perf_counter()
+        m0 = gift.evaluate_placement(g, x, net_ptr, pin_cell)
+        ev_ms = (time.perf_counter() - t0) * 1e3
+        m1 = gift.evaluate_placement(g, y, net_ptr, pin_cell)
+        out["placement_metrics"] = {
+            "initial": {k: [round(float(v), 6) for v in m0[k]] for k in m0},
+            "filtered": {k: [round(float(v), 6) for v in m1[k]] for k in m1},
+            "evaluate_ms": round(ev_ms, 3)}
     g.close()
     if not args.no_extra:
         out["batched"] = [bench_batched(gift, W, torch, st) for st in ("f32", "bf16")]

@@ -220,6 +220,38 @@ gift_status gift_graph_export_normalised(const gift_graph *graph, double sigma, 
  */
 gift_status gift_destroy_graph(gift_graph *graph, void *stream);
 
+/*
+ * gift_evaluate_placement -- placement metrics of a signal g (num_cols
+ * columns, e.g. x and y) on a resident graph, in float64, per column:
+ *
+ *   smoothness[q]  S(g_q) = sum over edges w_ij (g_i - g_j)^2: the smoothness
+ *                  of Section 2.1 (eq. smoothness), whose sum over the x and y
+ *                  columns is the weighted quadratic wirelength of Section 2.2
+ *                  (eq. wire_eq).  Star nodes count at the mean of their cells,
+ *                  which gives exactly the clique model's value, so S does not
+ *                  depend on the star threshold (up to rounding).
+ *   norm2[q]       sum_i g_i^2; S / norm2 is the Rayleigh quotient
+ *                  (eq. smoothness_ray).
+ *   hpwl[q]        sum over nets of (max - min) of g over the net's pins: the
+ *                  half-perimeter wirelength the paper evaluates placements
+ *                  with.  Needs the netlist: net_ptr int64[num_nets + 1] and
+ *                  pin_cell int32[num_pins] in device memory (offsets are
+ *                  clamped to [0, num_pins); pins outside [0, N) are skipped).
+ *
+ *   x        device, N x num_cols (num_cols in [1, 128]), leading dimension
+ *            ld, dtype F32 or F64.
+ *   Any of smoothness / norm2 / hpwl may be NULL (host double[num_cols]);
+ *   with hpwl NULL the netlist is not read.
+ *
+ * Sums are formed in a fixed order (deterministic).  Synchronises `stream`.
+ * Errors: GIFT_EINVAL, GIFT_EUNSUPPORTED (dtype), GIFT_ENOMEM, GIFT_EDEVICE.
+ */
+gift_status gift_evaluate_placement(const gift_graph *graph, const void *x, int32_t num_cols,
+                                    int64_t ld, int32_t dtype, const int64_t *net_ptr,
+                                    const int32_t *pin_cell, int64_t num_nets, int64_t num_pins,
+                                    double *smoothness, double *norm2, double *hpwl,
+                                    void *stream);
+
 /* ------------------------------------------------------------------------
  * Batched filtering: many resident graphs (designs of any sizes) filtered
  * with the same terms and column count by one launch sequence, captured

@@ -60,6 +60,7 @@ typedef struct {
   double *w;           /* nnz */
   double *deg;         /* R */
   int64_t num_nets;
+  int weight_model;
   int64_t *ucell_ptr;  /* E + 1: sorted distinct cells of every net */
   int32_t *ucell;
   int32_t *virt_net;   /* V: the net each virtual row stands for */
@@ -123,6 +124,7 @@ int oracle_build(int64_t num_cells, int64_t num_nets, int64_t num_pins,
   if (!g) return ORACLE_ENOMEM;
   g->num_cells = num_cells;
   g->num_nets = num_nets;
+  g->weight_model = weight_model;
   g->ucell_ptr = (int64_t *)malloc(sizeof(int64_t) * (size_t)(num_nets + 1));
   g->ucell = (int32_t *)malloc(sizeof(int32_t) * (size_t)(num_pins > 0 ? num_pins : 1));
   if (!g->ucell_ptr || !g->ucell) { oracle_free(g); return ORACLE_ENOMEM; }
@@ -330,4 +332,47 @@ int oracle_filter(const oracle_graph *g, int64_t num_terms, const double *sigma,
 out:
   free(x0); free(xa); free(xb); free(saved); free(a); free(delta); free(done);
   return status;
+}
+
+/* Placement metrics of g (N x c, ld = c) on the netlist the graph was built
+ * from, per column q, in float64:
+ *   S[q]     = sum over nets e with M_e >= 2 distinct cells and over the pairs
+ *              c < c' of its cells of w(M_e) (g_c - g_c')^2: the weighted
+ *              quadratic wirelength of Section 2.2 (eq. wire_eq) under the
+ *              clique net model, i.e. the smoothness g^T L g of eq. smoothness
+ *              on the clique-model graph (whatever the star threshold: a star
+ *              with its node at the mean of its cells has the same value);
+ *   norm2[q] = sum_i g_i^2, so S / norm2 is the Rayleigh quotient of
+ *              eq. smoothness_ray;
+ *   hpwl[q]  = sum over those nets of max - min of g over the net's cells
+ *              (half-perimeter wirelength, the paper's evaluation metric).
+ * Sums run in ascending net, then cell, order. */
+int oracle_evaluate(const oracle_graph *g, const double *x, int64_t c, double *S,
+                    double *norm2, double *hpwl) {
+  if (c < 1) return ORACLE_EINVAL;
+  for (int64_t q = 0; q < c; ++q) {
+    double s = 0.0, h = 0.0, n2 = 0.0;
+    for (int64_t e = 0; e < g->num_nets; ++e) {
+      int64_t lo = g->ucell_ptr[e], hi = g->ucell_ptr[e + 1];
+      int64_t m = hi - lo;
+      if (m < 2) continue;
+      double w = clique_weight(m, g->weight_model);
+      double mn = x[(int64_t)g->ucell[lo] * c + q], mx = mn;
+      for (int64_t a = lo; a < hi; ++a) {
+        double ga = x[(int64_t)g->ucell[a] * c + q];
+        if (ga < mn) mn = ga;
+        if (ga > mx) mx = ga;
+        for (int64_t b = a + 1; b < hi; ++b) {
+          double d = ga - x[(int64_t)g->ucell[b] * c + q];
+          s = s + w * (d * d);
+        }
+      }
+      h = h + (mx - mn);
+    }
+    for (int64_t i = 0; i < g->num_cells; ++i) n2 = n2 + x[i * c + q] * x[i * c + q];
+    S[q] = s;
+    norm2[q] = n2;
+    hpwl[q] = h;
+  }
+  return ORACLE_OK;
 }

@@ -40,6 +40,8 @@ def load(path: Optional[str] = None):
     lib.oracle_normalise.restype = C.c_int
     lib.oracle_filter.argtypes = [vp, i64, vp, vp, vp, vp, i64, vp, vp]
     lib.oracle_filter.restype = C.c_int
+    lib.oracle_evaluate.argtypes = [vp, vp, i64, vp, vp, vp]
+    lib.oracle_evaluate.restype = C.c_int
     if path is None:
         _lib = lib
     return lib
@@ -116,6 +118,21 @@ class OracleGraph:
         if rc:
             raise OracleError(f"oracle_filter failed ({rc})")
         return y
+
+
+    def evaluate(self, x: np.ndarray):
+        """Per-column (S, norm2, hpwl) of the placement x (see oracle_evaluate)."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        if x.ndim == 1:
+            x = x[:, None]
+        if x.shape[0] != self.num_cells:
+            raise OracleError("signal rows != cells")
+        c = x.shape[1]
+        S, n2, h = (np.empty(c, dtype=np.float64) for _ in range(3))
+        rc = self.lib.oracle_evaluate(self.handle, _ptr(x), c, _ptr(S), _ptr(n2), _ptr(h))
+        if rc:
+            raise OracleError(f"oracle_evaluate failed ({rc})")
+        return S, n2, h
 
 
 def build_graph(num_cells: int, net_ptr: np.ndarray, pin_cell: np.ndarray, *,

@@ -7,6 +7,6 @@
 ``libgift.so``; importing this package does not require a GPU, calling it
 does.
 """
-from .api import (Batch, Graph, Server, build_graph, filter_placement, make_terms,  # noqa: F401
-                  profile_collect, profile_enable)
+from .api import (Batch, Graph, Server, build_graph, evaluate_placement,  # noqa: F401
+                  filter_placement, make_terms, profile_collect, profile_enable)
 from ._lib import GiftError, lib  # noqa: F401

@@ -178,6 +178,42 @@ def filter_placement(graph: Graph, sigma: Sequence[float], order: Sequence[int],
     return out
 
 
+def evaluate_placement(graph: Graph, x: torch.Tensor, net_ptr=None, pin_cell=None,
+                       stream=None) -> dict:
+    """Per-column smoothness S (eq. smoothness / wire_eq), squared norm,
+    Rayleigh quotient S / norm2 (eq. smoothness_ray) and, when the netlist is
+    given (numpy or CUDA tensors), half-perimeter wirelength, in float64."""
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dim() == 2):
+        raise TypeError("x must be a 2-D CUDA tensor")
+    if x.dtype not in TORCH_DTYPES:
+        raise TypeError("x must be float32 or float64")
+    if x.stride(1) != 1:
+        x = x.contiguous()
+    n, c = x.shape
+    if n != graph.info()["num_cells"]:
+        raise ValueError("x rows != graph cells")
+    S = np.zeros(c)
+    n2 = np.zeros(c)
+    h = np.zeros(c) if net_ptr is not None else None
+    np_d = pc_d = None
+    E = P = 0
+    if net_ptr is not None:
+        np_d = torch.as_tensor(np.asarray(net_ptr, dtype=np.int64) if not isinstance(
+            net_ptr, torch.Tensor) else net_ptr, device=x.device).to(torch.int64).contiguous()
+        pc_d = torch.as_tensor(np.asarray(pin_cell, dtype=np.int32) if not isinstance(
+            pin_cell, torch.Tensor) else pin_cell, device=x.device).to(torch.int32).contiguous()
+        E = np_d.shape[0] - 1
+        P = pc_d.shape[0]
+    L.check(L.lib().gift_evaluate_placement(graph.handle, _ptr(x), c, x.stride(0),
+                                            TORCH_DTYPES[x.dtype], _ptr(np_d), _ptr(pc_d), E, P,
+                                            _ptr(S), _ptr(n2), _ptr(h), _stream_handle(stream)),
+            "gift_evaluate_placement")
+    out = {"smoothness": S, "norm2": n2, "rayleigh": S / np.where(n2 > 0, n2, 1.0)}
+    if h is not None:
+        out["hpwl"] = h
+    return out
+
+
 class Batch:
     """Many resident graphs filtered with the same terms and column count by
     one captured launch sequence (``gift_batch_create``).  The graphs must

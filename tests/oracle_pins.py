@@ -285,7 +285,68 @@ def pin_invalid_input(lib):
         g.filter(np.zeros((2, 1)), [1.0], [0], [1.0])
 
 
+def _dense_laplacian_from_netlist(n, net_ptr, pin_cell, model):
+    """L = D - A of the clique model, accumulated straight from the netlist:
+    every net of M >= 2 distinct cells adds w(M) to each pair."""
+    a = np.zeros((n, n))
+    for e in range(len(net_ptr) - 1):
+        cells = sorted(set(int(c) for c in pin_cell[net_ptr[e]:net_ptr[e + 1]]))
+        m = len(cells)
+        if m < 2:
+            continue
+        w = 2.0 / m if model == O.W_TWO_OVER_M else 1.0 / (m - 1)
+        for i in cells:
+            for j in cells:
+                if i != j:
+                    a[i, j] += w
+    return np.diag(a.sum(axis=1)) - a
+
+
+def pin_evaluate_hand(lib):
+    """Hand-computed metrics: nets {0,1,2}, {2,3}, a 1-pin net and a net whose
+    two pins are one cell; x = (0, 3, 7, 1), y = (2, 2, 5, 0).
+    S_x = (9 + 49 + 16) / 2 + 36 = 73, S_y = (0 + 9 + 9) / 2 + 25 = 34,
+    HPWL_x = 7 + 6 = 13, HPWL_y = 3 + 5 = 8, |x|^2 = 59, |y|^2 = 33."""
+    net_ptr = np.array([0, 3, 5, 6, 8], dtype=np.int64)
+    pins = np.array([0, 1, 2, 2, 3, 1, 3, 3], dtype=np.int32)
+    g = O.build_graph(4, net_ptr, pins, lib=lib)
+    x = np.array([[0.0, 2.0], [3.0, 2.0], [7.0, 5.0], [1.0, 0.0]])
+    S, n2, h = g.evaluate(x)
+    assert np.array_equal(S, [73.0, 34.0]), S
+    assert np.array_equal(n2, [59.0, 33.0]), n2
+    assert np.array_equal(h, [13.0, 8.0]), h
+    g.close()
+
+
+def pin_evaluate_dense(lib):
+    """S equals trace(G^T L G) with L = D - A built densely from the netlist
+    (eq. smoothness, eq. wire_eq), for both weight models and any star
+    threshold; the Rayleigh quotient of each Laplacian eigenvector is its
+    eigenvalue (eq. smoothness_ray2); S and HPWL do not change when the whole
+    placement moves."""
+    rng = np.random.default_rng(21)
+    for trial in range(6):
+        n = int(rng.integers(3, 14))
+        net_ptr, pins = _random_netlist(rng, n, int(rng.integers(1, 9)), 6)
+        model = trial % 2
+        L = _dense_laplacian_from_netlist(n, net_ptr, pins, model)
+        x = rng.normal(size=(n, 3)) * 5
+        for T in (0, 2):
+            g = O.build_graph(n, net_ptr, pins, weight_model=model, star_threshold=T, lib=lib)
+            S, n2, h = g.evaluate(x)
+            exp = np.einsum("iq,ij,jq->q", x, L, x)
+            assert np.allclose(S, exp, rtol=1e-12, atol=1e-9), (trial, T, S, exp)
+            assert np.allclose(n2, (x * x).sum(axis=0), rtol=1e-14)
+            S2, _, h2 = g.evaluate(x + 17.5)
+            assert np.allclose(S2, S, rtol=1e-9, atol=1e-7) and np.allclose(h2, h, rtol=1e-12)
+            lam, U = np.linalg.eigh(L)
+            SU, nU, _ = g.evaluate(U)
+            assert np.allclose(SU / nU, lam, rtol=1e-9, atol=1e-9), (SU / nU, lam)
+            g.close()
+
+
 ALL_PINS = [pin_golden_two_cell, pin_clique_closed_form, pin_hand_built,
             pin_brute_force_structure, pin_spectral, pin_theorem1_fixed_point,
             pin_spectrum, pin_isolated_and_fixed, pin_star_schur,
-            pin_generated_invariants, pin_invalid_input]
+            pin_generated_invariants, pin_invalid_input, pin_evaluate_hand,
+            pin_evaluate_dense]

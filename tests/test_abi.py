@@ -187,3 +187,10 @@ def test_server_arguments_rejected_without_device_work():
     st = L.ServerStats()
     assert lib.gift_server_get_stats(None, 0, C.byref(st)) == L.GIFT_EINVAL
     assert lib.gift_server_destroy(None) == L.GIFT_OK
+
+
+def test_evaluate_arguments_rejected_without_device_work():
+    lib = L.lib()
+    out = (C.c_double * 2)()
+    assert lib.gift_evaluate_placement(None, None, 2, 2, 0, None, None, 0, 0, out, None, None,
+                                       None) == L.GIFT_EINVAL

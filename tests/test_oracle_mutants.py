@@ -27,6 +27,8 @@ MUTANTS = {
     "virtual_mean_off_by_one": ("sum / (double)(hi - lo)", "sum / (double)(hi - lo + 1)"),
     "self_loop_unscaled": ("delta[i] = (sigma * s[i]) * s[i];", "delta[i] = sigma * s[i];"),
     "fixed_rows_not_restored": ("(fixed && fixed[i]) ? x_in[i * c + q] : acc", "acc"),
+    "wirelength_unweighted": ("s = s + w * (d * d);", "s = s + (d * d);"),
+    "hpwl_min_not_tracked": ("if (ga < mn) mn = ga;", "if (ga < mn) mx = ga;"),
 }
 
 
