@@ -391,6 +391,15 @@ def main():
         m0 = gift.evaluate_placement(g, x, net_ptr, pin_cell)
         ev_ms = (time.perf_counter() - t0) * 1e3
         m1 = gift.evaluate_placement(g, y, net_ptr, pin_cell)
+        # the exact filter (I + L~_4)^-1 g that the paper's filter approximates
+        for _ in range(2):
+            gift.filter_exact(g, 4.0, x, tol=1e-6)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ye, its = gift.filter_exact(g, 4.0, x, tol=1e-6)
+        ex_ms = (time.perf_counter() - t0) * 1e3
+        out["exact_filter"] = {"sigma": 4.0, "tol": 1e-6, "iterations": its,
+                               "ms": round(ex_ms, 3)}
         out["placement_metrics"] = {
             "initial": {k: [round(float(v), 6) for v in m0[k]] for k in m0},
             "filtered": {k: [round(float(v), 6) for v in m1[k]] for k in m1},

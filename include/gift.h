@@ -186,6 +186,33 @@ gift_status gift_filter_placement(const gift_graph *graph, const gift_term *term
                                   int64_t ld_out, int32_t out_dtype,
                                   const uint8_t *fixed_mask, void *stream);
 
+/*
+ * gift_filter_exact -- the exact filter the paper's filter approximates
+ * (Section 3.2.2: eq. incremental, eq. derivative, eq. spectral):
+ *
+ *     g' = (I + L~_sigma)^-1 g,   L~_sigma = I - A~_sigma,
+ *
+ * i.e. the solution of (2 I - A~_sigma) g' = g over all graph rows (star
+ * rows start from the mean of their cells, as in the filter; only cell rows
+ * are returned).  Solved per column by conjugate gradients from g' = 0 until
+ * ||r|| <= tol ||g|| or max_iter iterations; each iteration is one SpMM pass
+ * (the filter's kernel) and float64 dot products.  The matrix has
+ * eigenvalues in [1, 3), so a few dozen iterations reach 1e-12.
+ *
+ *   sigma       a self-loop weight prepared in the graph.
+ *   x_in, y_out, fixed_mask, dtypes: as in gift_filter_placement.
+ *   tol         relative residual (> 0); max_iter >= 1.
+ *   iterations  (nullable) iterations of the slowest column chunk.
+ *
+ * The graph must use F32 or F64 storage (GIFT_EUNSUPPORTED otherwise): the
+ * iterates are kept in the storage type.  Synchronises `stream` (the host
+ * checks convergence).  Errors as in gift_filter_placement.
+ */
+gift_status gift_filter_exact(const gift_graph *graph, double sigma, const void *x_in,
+                              int32_t num_cols, int64_t ld_in, int32_t in_dtype, void *y_out,
+                              int64_t ld_out, int32_t out_dtype, const uint8_t *fixed_mask,
+                              double tol, int64_t max_iter, int64_t *iterations, void *stream);
+
 /* Prepare one more self-loop weight (sigma >= 0).  No-op if already there.
  * Asynchronous on `stream`, like the tail of gift_build_graph. */
 gift_status gift_graph_add_sigma(gift_graph *graph, double sigma, void *stream);

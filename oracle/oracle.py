@@ -42,6 +42,8 @@ def load(path: Optional[str] = None):
     lib.oracle_filter.restype = C.c_int
     lib.oracle_evaluate.argtypes = [vp, vp, i64, vp, vp, vp]
     lib.oracle_evaluate.restype = C.c_int
+    lib.oracle_filter_exact.argtypes = [vp, C.c_double, vp, i64, C.c_double, i64, vp, vp, vp]
+    lib.oracle_filter_exact.restype = C.c_int
     if path is None:
         _lib = lib
     return lib
@@ -119,6 +121,24 @@ class OracleGraph:
             raise OracleError(f"oracle_filter failed ({rc})")
         return y
 
+
+    def filter_exact(self, x: np.ndarray, sigma: float, tol: float = 1e-14,
+                     max_iter: int = 1000, fixed: Optional[np.ndarray] = None):
+        """(I + L~_sigma)^-1 x by conjugate gradients (see oracle_filter_exact);
+        returns (y, iterations)."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        if x.ndim == 1:
+            x = x[:, None]
+        if x.shape[0] != self.num_cells:
+            raise OracleError("signal rows != cells")
+        fx = None if fixed is None else np.ascontiguousarray(fixed, dtype=np.uint8)
+        y = np.empty_like(x)
+        it = np.zeros(1, dtype=np.int64)
+        rc = self.lib.oracle_filter_exact(self.handle, float(sigma), _ptr(x), x.shape[1],
+                                          float(tol), int(max_iter), _ptr(fx), _ptr(y), _ptr(it))
+        if rc:
+            raise OracleError(f"oracle_filter_exact failed ({rc})")
+        return y, int(it[0])
 
     def evaluate(self, x: np.ndarray):
         """Per-column (S, norm2, hpwl) of the placement x (see oracle_evaluate)."""

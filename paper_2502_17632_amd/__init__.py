@@ -8,5 +8,6 @@
 does.
 """
 from .api import (Batch, Graph, Server, build_graph, evaluate_placement,  # noqa: F401
-                  filter_placement, make_terms, profile_collect, profile_enable)
+                  filter_exact, filter_placement, make_terms, profile_collect,
+                  profile_enable)
 from ._lib import GiftError, lib  # noqa: F401

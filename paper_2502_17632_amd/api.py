@@ -178,6 +178,35 @@ def filter_placement(graph: Graph, sigma: Sequence[float], order: Sequence[int],
     return out
 
 
+def filter_exact(graph: Graph, sigma: float, x: torch.Tensor, *, tol: float = 1e-6,
+                 max_iter: int = 500, fixed: Optional[torch.Tensor] = None,
+                 out: Optional[torch.Tensor] = None, out_dtype: torch.dtype = torch.float32,
+                 stream=None) -> Tuple[torch.Tensor, int]:
+    """g' = (I + L~_sigma)^-1 x by conjugate gradients; returns (g', iterations)."""
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dim() == 2):
+        raise TypeError("x must be a 2-D CUDA tensor")
+    if x.stride(1) != 1:
+        x = x.contiguous()
+    if x.dtype not in TORCH_DTYPES:
+        raise TypeError("x must be float32 or float64")
+    n, c = x.shape
+    if n != graph.info()["num_cells"]:
+        raise ValueError("x rows != graph cells")
+    if out is None:
+        out = torch.empty((n, c), dtype=out_dtype, device=x.device)
+    if fixed is not None:
+        if not (fixed.is_cuda and fixed.dtype == torch.uint8 and fixed.numel() == n):
+            raise TypeError("fixed must be a uint8 CUDA tensor with one entry per cell")
+        fixed = fixed.contiguous()
+    it = C.c_int64()
+    L.check(L.lib().gift_filter_exact(graph.handle, float(sigma), _ptr(x), c, x.stride(0),
+                                      TORCH_DTYPES[x.dtype], _ptr(out), out.stride(0),
+                                      TORCH_DTYPES[out.dtype], _ptr(fixed), float(tol),
+                                      int(max_iter), C.byref(it), _stream_handle(stream)),
+            "gift_filter_exact")
+    return out, it.value
+
+
 def evaluate_placement(graph: Graph, x: torch.Tensor, net_ptr=None, pin_cell=None,
                        stream=None) -> dict:
     """Per-column smoothness S (eq. smoothness / wire_eq), squared norm,

@@ -564,6 +564,246 @@ size_t chunk_buffer_bytes(const FilterPlan &pl, int C) {
   return carve_chunk_buffers(pl, C, nullptr, &bf);
 }
 
+// ---------------------------------------------------------------------------
+// The exact filter g' = (I + L~_sigma)^-1 g (Section 3.2.2, eq. derivative
+// and eq. spectral) that the paper's filter approximates: conjugate gradients
+// on (2 I - A~_sigma) g' = g over all R rows, per column, from g' = 0.  One
+// iteration is an SpMM pass (the same kernel as the filter) and three fused
+// vector kernels; dot products are float64, summed per block over fixed
+// ranges and then in block order (deterministic).  The scalars stay on the
+// device; the host reads the residuals every few iterations to stop.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kCgBlocks = 1024;  // blocks of the vector kernels (fixed ranges)
+
+__device__ __forceinline__ void cg_range(int64_t n, int64_t *lo, int64_t *hi) {
+  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+  *lo = static_cast<int64_t>(blockIdx.x) * per;
+  *hi = *lo + per < n ? *lo + per : n;
+}
+
+// Sums v[C] over the block (fixed tree) and writes part[block * C + q].
+template <int C>
+__device__ __forceinline__ void cg_block_sum(double (&v)[C], double *red, double *part) {
+#pragma unroll
+  for (int q = 0; q < C; ++q) {
+    red[threadIdx.x] = v[q];
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+      if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x * C + q] = red[0];
+    __syncthreads();
+  }
+}
+
+// out[q] = sum of part[b * C + q] over b in order.
+template <int C>
+__global__ void k_cg_reduce(const double *part, int nb, double *out) {
+  const int q = threadIdx.x;
+  if (q >= C) return;
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += part[b * C + q];
+  out[q] = s;
+}
+
+// x = 0, r = p = b; part = b . b
+template <int D, int C>
+__global__ __launch_bounds__(kBlock) void k_cg_init(const typename Store<D>::T *b,
+                                                    typename Store<D>::T *x,
+                                                    typename Store<D>::T *r,
+                                                    typename Store<D>::T *p, int64_t R,
+                                                    double *part) {
+  __shared__ double red[kBlock];
+  int64_t lo, hi;
+  cg_range(R, &lo, &hi);
+  double acc[C] = {};
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
+      const auto v = b[i * C + q];
+      x[i * C + q] = Store<D>::from_f64(0.0);
+      r[i * C + q] = v;
+      p[i * C + q] = v;
+      const double d = static_cast<double>(Store<D>::load(v));
+      acc[q] += d * d;
+    }
+  }
+  cg_block_sum<C>(acc, red, part);
+}
+
+// q = 2 p - q (q holds A~ p); part = p . q
+template <int D, int C>
+__global__ __launch_bounds__(kBlock) void k_cg_q(const typename Store<D>::T *p,
+                                                 typename Store<D>::T *q, int64_t R,
+                                                 double *part) {
+  using S = Store<D>;
+  __shared__ double red[kBlock];
+  int64_t lo, hi;
+  cg_range(R, &lo, &hi);
+  double acc[C] = {};
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const typename S::A pv = S::load(p[i * C + c]);
+      const typename S::A qv = 2 * pv - S::load(q[i * C + c]);
+      q[i * C + c] = S::from_acc(qv);
+      acc[c] += static_cast<double>(pv) * static_cast<double>(qv);
+    }
+  }
+  cg_block_sum<C>(acc, red, part);
+}
+
+// alpha = rho / pq; x += alpha p; r -= alpha q; part = r . r
+template <int D, int C>
+__global__ __launch_bounds__(kBlock) void k_cg_update(typename Store<D>::T *x,
+                                                      typename Store<D>::T *r,
+                                                      const typename Store<D>::T *p,
+                                                      const typename Store<D>::T *q,
+                                                      const double *rho, const double *pq,
+                                                      int64_t R, double *part) {
+  using S = Store<D>;
+  using A = typename S::A;
+  __shared__ double red[kBlock];
+  A alpha[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) alpha[c] = static_cast<A>(pq[c] > 0.0 ? rho[c] / pq[c] : 0.0);
+  int64_t lo, hi;
+  cg_range(R, &lo, &hi);
+  double acc[C] = {};
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int64_t k = i * C + c;
+      x[k] = S::from_acc(S::load(x[k]) + alpha[c] * S::load(p[k]));
+      const A rv = S::load(r[k]) - alpha[c] * S::load(q[k]);
+      r[k] = S::from_acc(rv);
+      acc[c] += static_cast<double>(rv) * static_cast<double>(rv);
+    }
+  }
+  cg_block_sum<C>(acc, red, part);
+}
+
+// beta = rho_new / rho; p = r + beta p
+template <int D, int C>
+__global__ __launch_bounds__(kBlock) void k_cg_p(const typename Store<D>::T *r,
+                                                 typename Store<D>::T *p, const double *rho,
+                                                 const double *rho_new, int64_t R) {
+  using S = Store<D>;
+  using A = typename S::A;
+  A beta[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) beta[c] = static_cast<A>(rho[c] > 0.0 ? rho_new[c] / rho[c] : 0.0);
+  int64_t lo, hi;
+  cg_range(R, &lo, &hi);
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int64_t k = i * C + c;
+      p[k] = S::from_acc(S::load(r[k]) + beta[c] * S::load(p[k]));
+    }
+  }
+}
+
+// y_out[cells] = x (fixed rows copied from x_in)
+template <int D, int C>
+__global__ void k_cg_out(const typename Store<D>::T *x, int64_t N, GraphIO io, int32_t in_dt,
+                         int32_t out_dt, int32_t col0) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= N * C) return;
+  const int64_t r = i / C;
+  const int c = static_cast<int>(i % C);
+  double v = static_cast<double>(Store<D>::load(x[i]));
+  if (io.fixed && to_global(io.fixed)[r]) v = load_in(io.x_in, in_dt, r * io.ld_in + col0 + c);
+  const int64_t o = r * io.ld_out + col0 + c;
+  if (out_dt == GIFT_F64) to_global(static_cast<double *>(io.y_out))[o] = v;
+  else to_global(static_cast<float *>(io.y_out))[o] = static_cast<float>(v);
+}
+
+template <int D, int C>
+gift_status exact_chunk(const gift_graph *g, const FilterPlan &pl, double tol, int64_t max_iter,
+                        int32_t col0, hipStream_t st, int64_t *iters) {
+  using T = typename Store<D>::T;
+  const int64_t R = pl.R;
+  const size_t vb = static_cast<size_t>(R) * C;
+  Scratch sc(st);
+  T *b = nullptr, *x = nullptr, *r = nullptr, *p = nullptr, *q = nullptr;
+  double *part = nullptr, *dots = nullptr;
+  GIFT_TRY(sc.get(&b, vb, "cg right-hand side"));
+  GIFT_TRY(sc.get(&x, vb, "cg solution"));
+  GIFT_TRY(sc.get(&r, vb, "cg residual"));
+  GIFT_TRY(sc.get(&p, vb, "cg direction"));
+  GIFT_TRY(sc.get(&q, vb, "cg product"));
+  GIFT_TRY(sc.get(&part, static_cast<size_t>(kCgBlocks) * C, "cg partial dots"));
+  // dots: bb | rho (two slots, swapped every iteration) | pq
+  GIFT_TRY(sc.get(&dots, 4 * C, "cg scalars"));
+  double *bb = dots, *rho[2] = {dots + C, dots + 2 * C}, *pq = dots + 3 * C;
+  const unsigned nb = static_cast<unsigned>(std::min<int64_t>(kCgBlocks, (R + kBlock - 1) / kBlock));
+  k_prep<D, C, false><<<static_cast<unsigned>(pl.num_tiles), kBlock, 0, st>>>(
+      launch_args(pl, pl.groups.front(), false), pl.in_dtype, col0, b);
+  GIFT_TRY(check_launch("k_prep"));
+  k_cg_init<D, C><<<nb, kBlock, 0, st>>>(b, x, r, p, R, part);
+  GIFT_TRY(check_launch("k_cg_init"));
+  k_cg_reduce<C><<<1, kWave, 0, st>>>(part, nb, bb);
+  GIFT_TRY(check_launch("k_cg_reduce"));
+  GIFT_HIP(hipMemcpyAsync(rho[0], bb, sizeof(double) * C, hipMemcpyDeviceToDevice, st));
+  const LaunchArgs l = launch_args(pl, pl.groups.front(), false);
+  std::vector<double> h(2 * C);
+  int64_t it = 0;
+  int cur = 0;
+  bool done = false;
+  while (!done && it < max_iter) {
+    GIFT_TRY(launch_timed(k_spmm<D, C, false, 0, false>, static_cast<unsigned>(pl.num_tiles), st,
+                          pl.profile, GIFT_PROF_SPMM, pass_bytes(pl, C, false), "k_spmm", l,
+                          static_cast<const void *>(p), static_cast<void *>(q), FinalArgs{}));
+    k_cg_q<D, C><<<nb, kBlock, 0, st>>>(p, q, R, part);
+    GIFT_TRY(check_launch("k_cg_q"));
+    k_cg_reduce<C><<<1, kWave, 0, st>>>(part, nb, pq);
+    k_cg_update<D, C><<<nb, kBlock, 0, st>>>(x, r, p, q, rho[cur], pq, R, part);
+    GIFT_TRY(check_launch("k_cg_update"));
+    k_cg_reduce<C><<<1, kWave, 0, st>>>(part, nb, rho[cur ^ 1]);
+    k_cg_p<D, C><<<nb, kBlock, 0, st>>>(r, p, rho[cur], rho[cur ^ 1], R);
+    GIFT_TRY(check_launch("k_cg_p"));
+    cur ^= 1;
+    ++it;
+    if (it % 4 == 0 || it == max_iter) {
+      GIFT_HIP(hipMemcpyAsync(h.data(), bb, sizeof(double) * C, hipMemcpyDeviceToHost, st));
+      GIFT_HIP(hipMemcpyAsync(h.data() + C, rho[cur], sizeof(double) * C,
+                              hipMemcpyDeviceToHost, st));
+      GIFT_HIP(hipStreamSynchronize(st));
+      done = true;
+      for (int c = 0; c < C; ++c)
+        if (h[C + c] > tol * tol * h[c]) done = false;
+    }
+  }
+  if (it > *iters) *iters = it;
+  const int64_t N = pl.cell_rows;
+  if (N > 0) {
+    k_cg_out<D, C><<<grid_for(N * C), kBlock, 0, st>>>(x, N, pl.one.io, pl.in_dtype,
+                                                         pl.out_dtype, col0);
+    GIFT_TRY(check_launch("k_cg_out"));
+  }
+  GIFT_HIP(hipStreamSynchronize(st));
+  return GIFT_OK;
+}
+
+template <int D>
+gift_status exact_chunk_c(const gift_graph *g, const FilterPlan &pl, int C, double tol,
+                          int64_t max_iter, int32_t col0, hipStream_t st, int64_t *iters) {
+  switch (C) {
+    case 1: return exact_chunk<D, 1>(g, pl, tol, max_iter, col0, st, iters);
+    case 2: return exact_chunk<D, 2>(g, pl, tol, max_iter, col0, st, iters);
+    case 4: return exact_chunk<D, 4>(g, pl, tol, max_iter, col0, st, iters);
+    case 8: return exact_chunk<D, 8>(g, pl, tol, max_iter, col0, st, iters);
+    case 16: return exact_chunk<D, 16>(g, pl, tol, max_iter, col0, st, iters);
+  }
+  return set_error(GIFT_EUNSUPPORTED, "column chunk %d", C);
+}
+
+}  // namespace
+
 }  // namespace gift
 
 using namespace gift;
@@ -615,5 +855,54 @@ extern "C" gift_status gift_filter_placement(const gift_graph *g, const gift_ter
     GIFT_TRY(enqueue_filter_chunk(pl, bf, C, col0, st));
     col0 += C;
   }
+  return GIFT_OK;
+}
+
+extern "C" gift_status gift_filter_exact(const gift_graph *g, double sigma, const void *x_in,
+                                         int32_t num_cols, int64_t ld_in, int32_t in_dt,
+                                         void *y_out, int64_t ld_out, int32_t out_dt,
+                                         const uint8_t *fixed, double tol, int64_t max_iter,
+                                         int64_t *iterations, void *stream) {
+  clear_error();
+  if (iterations) *iterations = 0;
+  if (!g) return set_error(GIFT_EINVAL, "gift_filter_exact: NULL graph");
+  if (num_cols < 1) return set_error(GIFT_EINVAL, "num_cols %d < 1", num_cols);
+  if (ld_in < num_cols || ld_out < num_cols)
+    return set_error(GIFT_EINVAL, "leading dimension smaller than num_cols");
+  if (in_dt != GIFT_F32 && in_dt != GIFT_F64)
+    return set_error(GIFT_EUNSUPPORTED, "in_dtype must be F32 or F64");
+  if (out_dt != GIFT_F32 && out_dt != GIFT_F64)
+    return set_error(GIFT_EUNSUPPORTED, "out_dtype must be F32 or F64");
+  if (g->storage != GIFT_F32 && g->storage != GIFT_F64)
+    return set_error(GIFT_EUNSUPPORTED, "the exact filter needs F32 or F64 storage");
+  if (!(tol > 0.0) || max_iter < 1) return set_error(GIFT_EINVAL, "tol must be > 0, max_iter >= 1");
+  gift_term term{sigma, 1, 0, 1.0};
+  FilterPlan pl;
+  GIFT_TRY(plan_groups(g, &term, 1, &pl.groups));
+  if (g->num_cells == 0) return GIFT_OK;
+  if (!x_in || !y_out) return set_error(GIFT_EINVAL, "x_in / y_out is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  pl.storage = g->storage;
+  pl.tile_class = 0;
+  pl.R = g->num_rows;
+  pl.nnz = g->nnz;
+  pl.cell_rows = g->num_cells;
+  pl.nnz_cells = g->nnz_cells;
+  pl.tiles = g->tiles[0];
+  pl.num_tiles = g->num_tiles[0];
+  pl.terms = &term;
+  pl.num_terms = 1;
+  pl.in_dtype = in_dt;
+  pl.out_dtype = out_dt;
+  pl.one = GraphDev{g->row_ptr, g->col, nullptr, nullptr, 0,
+                    GraphIO{x_in, ld_in, y_out, ld_out, fixed, g->num_cells}};
+  int64_t its = 0;
+  for (int32_t col0 = 0; col0 < num_cols;) {
+    const int C = chunk_width(num_cols - col0);
+    if (g->storage == GIFT_F64) GIFT_TRY(exact_chunk_c<GIFT_F64>(g, pl, C, tol, max_iter, col0, st, &its));
+    else GIFT_TRY(exact_chunk_c<GIFT_F32>(g, pl, C, tol, max_iter, col0, st, &its));
+    col0 += C;
+  }
+  if (iterations) *iterations = its;
   return GIFT_OK;
 }

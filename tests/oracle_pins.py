@@ -345,8 +345,53 @@ def pin_evaluate_dense(lib):
             g.close()
 
 
+def pin_exact_filter(lib):
+    """The exact filter (I + L~_sigma)^-1 g of eq. derivative / eq. spectral:
+    the conjugate-gradient result equals a dense solve of (2I - A~_sigma) g' = g
+    and the spectral form U diag(1 / (2 - mu)) U^T g; on the two-cell example
+    (A~_s = [[s, 1], [1, s]] / (1 + s)) the solution is known in closed form."""
+    rng = np.random.default_rng(33)
+    for trial in range(5):
+        n = int(rng.integers(3, 14))
+        net_ptr, pins = _random_netlist(rng, n, int(rng.integers(1, 9)), 6)
+        T = 0 if trial % 2 == 0 else 3
+        g = O.build_graph(n, net_ptr, pins, star_threshold=T, lib=lib)
+        sigma = [0.5, 2.0, 4.0][trial % 3]
+        x = rng.normal(size=(n, 2)) * 3
+        y, it = g.filter_exact(x, sigma)
+        a, d = g.normalise(sigma)
+        At = _dense_from(g)
+        for i in range(g.num_rows):
+            for p in range(g.row_ptr[i], g.row_ptr[i + 1]):
+                At[i, g.col[p]] = a[p]
+        At[np.diag_indices(g.num_rows)] = d
+        xe = np.zeros((g.num_rows, 2))
+        xe[:n] = x
+        for v in range(g.num_virtual):
+            e = int(g.virt_net[v])
+            cells = sorted(set(int(c) for c in pins[net_ptr[e]:net_ptr[e + 1]]))
+            xe[n + v] = x[cells].mean(axis=0)
+        M = 2 * np.eye(g.num_rows) - At
+        ref = np.linalg.solve(M, xe)[:n]
+        assert np.allclose(y, ref, rtol=1e-11, atol=1e-11), (trial, np.abs(y - ref).max())
+        mu, U = np.linalg.eigh(At)
+        spec = (U @ np.diag(1.0 / (2.0 - mu)) @ U.T @ xe)[:n]
+        assert np.allclose(y, spec, rtol=1e-10, atol=1e-10)
+        assert it <= g.num_rows + 1
+        g.close()
+    # two cells, one net: (2I - A~_s) has eigenvalues 1 (on [1, 1]) and
+    # 2 - (s - 1)/(1 + s) (on [1, -1]), so g' = mean + (g - mean) (1 + s)/(s + 3)
+    g = O.build_graph(2, np.array([0, 2], dtype=np.int64), np.array([0, 1], dtype=np.int32),
+                      lib=lib)
+    for s in (0.5, 2.0, 4.0):
+        y, _ = g.filter_exact(np.array([[0.0], [1.0]]), s)
+        k = (1 + s) / (s + 3)
+        assert np.allclose(y[:, 0], [0.5 - 0.5 * k, 0.5 + 0.5 * k], rtol=1e-13, atol=1e-14)
+    g.close()
+
+
 ALL_PINS = [pin_golden_two_cell, pin_clique_closed_form, pin_hand_built,
             pin_brute_force_structure, pin_spectral, pin_theorem1_fixed_point,
             pin_spectrum, pin_isolated_and_fixed, pin_star_schur,
             pin_generated_invariants, pin_invalid_input, pin_evaluate_hand,
-            pin_evaluate_dense]
+            pin_evaluate_dense, pin_exact_filter]

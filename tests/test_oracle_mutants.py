@@ -29,6 +29,8 @@ MUTANTS = {
     "fixed_rows_not_restored": ("(fixed && fixed[i]) ? x_in[i * c + q] : acc", "acc"),
     "wirelength_unweighted": ("s = s + w * (d * d);", "s = s + (d * d);"),
     "hpwl_min_not_tracked": ("if (ga < mn) mn = ga;", "if (ga < mn) mx = ga;"),
+    "exact_filter_without_identity": ("q[i] = 2.0 * p[i] - acc;", "q[i] = p[i] - acc;"),
+    "cg_beta_inverted": ("double beta = rho_new / rho;", "double beta = rho / rho_new;"),
 }
 
 
