@@ -400,6 +400,14 @@ def main():
         ex_ms = (time.perf_counter() - t0) * 1e3
         out["exact_filter"] = {"sigma": 4.0, "tol": 1e-6, "iterations": its,
                                "ms": round(ex_ms, 3)}
+        box = (0.0, 0.0, W.DIE, W.DIE)
+        dens = {}
+        for name, sig in (("initial", x), ("filtered", y)):
+            d = gift.bin_density(sig, box, 512, 512, w0=1.0, h0=1.0)
+            dens[name] = {"max_over_bin_area": round(float(d.max()) / (W.DIE / 512) ** 2, 3),
+                          "overflow_at_1": round(gift.density_overflow(
+                              d, box, 1.0, float(nl.num_cells)), 5)}
+        out["bin_density_512"] = dens
         out["placement_metrics"] = {
             "initial": {k: [round(float(v), 6) for v in m0[k]] for k in m0},
             "filtered": {k: [round(float(v), 6) for v in m1[k]] for k in m1},

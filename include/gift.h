@@ -279,6 +279,35 @@ gift_status gift_evaluate_placement(const gift_graph *graph, const void *x, int3
                                     double *smoothness, double *norm2, double *hpwl,
                                     void *stream);
 
+/*
+ * gift_bin_density -- bin density of a placement (Section 2.2,
+ * eq. density_eq): the region [xl, xh] x [yl, yh] is cut into nbx x nby equal
+ * bins and
+ *
+ *     rho_b = sum_v l_x(v, b) l_y(v, b),
+ *
+ * the overlap area of bin b with each object's rectangle (width w_v, height
+ * h_v, centred at the object's position).  Shows how much a placement (e.g.
+ * the filtered one) overlaps, the over-smoothing the paper's multi-order
+ * filter is designed to limit.
+ *
+ *   x          device, num_objects x ld (ld >= 2): columns 0 and 1 are the
+ *              x and y centres, dtype F32 or F64.
+ *   widths, heights   device float64[num_objects], or NULL to use w0 / h0.
+ *   density    device float64[nby][nbx] (row-major, bin (i, j) at
+ *              [j * nbx + i]), overwritten.
+ *
+ * Overlaps are summed exactly in 64-bit fixed point (2^-40 of a bin's area),
+ * so the result is deterministic.  Objects with a non-finite position or a
+ * size <= 0 are skipped.  Asynchronous on `stream`.  Errors: GIFT_EINVAL
+ * (sizes, region, NULL buffers), GIFT_EUNSUPPORTED (dtype), GIFT_ENOMEM,
+ * GIFT_EDEVICE.
+ */
+gift_status gift_bin_density(const void *x, int64_t num_objects, int64_t ld, int32_t dtype,
+                             const double *widths, const double *heights, double w0,
+                             double h0, double xl, double yl, double xh, double yh,
+                             int32_t nbx, int32_t nby, double *density, void *stream);
+
 /* ------------------------------------------------------------------------
  * Batched filtering: many resident graphs (designs of any sizes) filtered
  * with the same terms and column count by one launch sequence, captured

@@ -453,3 +453,34 @@ out:
   free(a); free(delta); free(b); free(x); free(r); free(p); free(q);
   return status;
 }
+
+/* Bin density of a placement (Section 2.2, eq. density_eq): the placement
+ * region [xl, xh] x [yl, yh] is cut into nbx x nby equal bins and
+ *     rho_b = sum_v l_x(v, b) l_y(v, b),
+ * the overlap area of bin b with every object v, here the rectangle of width
+ * w_v and height h_v centred at the object's position (x_v, y_v).  Objects
+ * are the N cells of the graph; x is N x 2 (ld = 2).  density: nby x nbx,
+ * row-major (bin (i, j) covers column i and row j).  */
+int oracle_bin_density(int64_t n, const double *x, const double *w, const double *h,
+                       double xl, double yl, double xh, double yh, int64_t nbx, int64_t nby,
+                       double *density) {
+  if (nbx < 1 || nby < 1 || !(xh > xl) || !(yh > yl)) return ORACLE_EINVAL;
+  double bw = (xh - xl) / (double)nbx, bh = (yh - yl) / (double)nby;
+  for (int64_t k = 0; k < nbx * nby; ++k) density[k] = 0.0;
+  for (int64_t v = 0; v < n; ++v) {
+    double x0 = x[2 * v] - 0.5 * w[v], x1 = x[2 * v] + 0.5 * w[v];
+    double y0 = x[2 * v + 1] - 0.5 * h[v], y1 = x[2 * v + 1] + 0.5 * h[v];
+    for (int64_t j = 0; j < nby; ++j) {
+      double b0 = yl + (double)j * bh, b1 = b0 + bh;
+      double ly = (y1 < b1 ? y1 : b1) - (y0 > b0 ? y0 : b0);
+      if (ly <= 0.0) continue;
+      for (int64_t i = 0; i < nbx; ++i) {
+        double a0 = xl + (double)i * bw, a1 = a0 + bw;
+        double lx = (x1 < a1 ? x1 : a1) - (x0 > a0 ? x0 : a0);
+        if (lx <= 0.0) continue;
+        density[j * nbx + i] = density[j * nbx + i] + lx * ly;
+      }
+    }
+  }
+  return ORACLE_OK;
+}

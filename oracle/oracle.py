@@ -44,6 +44,9 @@ def load(path: Optional[str] = None):
     lib.oracle_evaluate.restype = C.c_int
     lib.oracle_filter_exact.argtypes = [vp, C.c_double, vp, i64, C.c_double, i64, vp, vp, vp]
     lib.oracle_filter_exact.restype = C.c_int
+    lib.oracle_bin_density.argtypes = [i64, vp, vp, vp, C.c_double, C.c_double, C.c_double,
+                                       C.c_double, i64, i64, vp]
+    lib.oracle_bin_density.restype = C.c_int
     if path is None:
         _lib = lib
     return lib
@@ -181,3 +184,19 @@ def build_graph(num_cells: int, net_ptr: np.ndarray, pin_cell: np.ndarray, *,
 
 def build_netlist(netlist, **kw) -> OracleGraph:
     return build_graph(netlist.num_cells, netlist.net_ptr, netlist.pin_cell, **kw)
+
+
+def bin_density(x: np.ndarray, w, h, box, nbx: int, nby: int, lib=None) -> np.ndarray:
+    """Bin density (see oracle_bin_density): x is N x 2 cell centres, w/h the
+    cell widths/heights (arrays or scalars), box = (xl, yl, xh, yh)."""
+    lib = lib or load()
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    n = x.shape[0]
+    w = np.ascontiguousarray(np.broadcast_to(np.asarray(w, dtype=np.float64), (n,)))
+    h = np.ascontiguousarray(np.broadcast_to(np.asarray(h, dtype=np.float64), (n,)))
+    out = np.empty((nby, nbx), dtype=np.float64)
+    rc = lib.oracle_bin_density(n, _ptr(x), _ptr(w), _ptr(h), float(box[0]), float(box[1]),
+                                float(box[2]), float(box[3]), int(nbx), int(nby), _ptr(out))
+    if rc:
+        raise OracleError(f"oracle_bin_density failed ({rc})")
+    return out

@@ -7,7 +7,8 @@
 ``libgift.so``; importing this package does not require a GPU, calling it
 does.
 """
-from .api import (Batch, Graph, Server, build_graph, evaluate_placement,  # noqa: F401
+from .api import (Batch, Graph, Server, bin_density, build_graph,  # noqa: F401
+                  density_overflow, evaluate_placement,
                   filter_exact, filter_placement, make_terms, profile_collect,
                   profile_enable)
 from ._lib import GiftError, lib  # noqa: F401

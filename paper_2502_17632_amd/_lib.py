@@ -148,6 +148,10 @@ SIGNATURES = {
                                     C.c_double, C.c_int64, C.POINTER(C.c_int64), C.c_void_p]),
     "gift_graph_get_info": (C.c_int, [C.c_void_p, C.POINTER(GraphInfo)]),
     "gift_graph_set_tile_class": (C.c_int, [C.c_void_p, C.c_int32]),
+    "gift_bin_density": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_int32, C.c_void_p,
+                                   C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double,
+                                   C.c_double, C.c_double, C.c_int32, C.c_int32, C.c_void_p,
+                                   C.c_void_p]),
     "gift_evaluate_placement": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int64,
                                           C.c_int32, C.c_void_p, C.c_void_p, C.c_int64,
                                           C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,

@@ -207,6 +207,40 @@ def filter_exact(graph: Graph, sigma: float, x: torch.Tensor, *, tol: float = 1e
     return out, it.value
 
 
+def bin_density(x: torch.Tensor, box: Sequence[float], nbx: int, nby: int, *,
+                widths: Optional[torch.Tensor] = None, heights: Optional[torch.Tensor] = None,
+                w0: float = 1.0, h0: float = 1.0, stream=None) -> torch.Tensor:
+    """Bin density map (eq. density_eq) of the centres x[:, 0:2] as an
+    nby x nbx float64 CUDA tensor; box = (xl, yl, xh, yh)."""
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dim() == 2 and x.shape[1] >= 2):
+        raise TypeError("x must be an N x (>= 2) CUDA tensor")
+    if x.dtype not in TORCH_DTYPES:
+        raise TypeError("x must be float32 or float64")
+    if x.stride(1) != 1:
+        x = x.contiguous()
+    n = x.shape[0]
+    for t in (widths, heights):
+        if t is not None and not (t.is_cuda and t.dtype == torch.float64 and t.numel() == n):
+            raise TypeError("widths/heights must be float64 CUDA tensors with one entry per object")
+    widths = None if widths is None else widths.contiguous()
+    heights = None if heights is None else heights.contiguous()
+    out = torch.empty((int(nby), int(nbx)), dtype=torch.float64, device=x.device)
+    xl, yl, xh, yh = (float(v) for v in box)
+    L.check(L.lib().gift_bin_density(_ptr(x), n, x.stride(0) if n else 2, TORCH_DTYPES[x.dtype],
+                                     _ptr(widths), _ptr(heights), float(w0), float(h0), xl, yl,
+                                     xh, yh, int(nbx), int(nby), _ptr(out),
+                                     _stream_handle(stream)), "gift_bin_density")
+    return out
+
+
+def density_overflow(density: torch.Tensor, box: Sequence[float], target: float,
+                     total_area: float) -> float:
+    """sum_b max(0, rho_b - target * bin area) / total object area."""
+    nby, nbx = density.shape
+    area = (box[2] - box[0]) / nbx * (box[3] - box[1]) / nby
+    return float(torch.clamp(density - target * area, min=0).sum().item() / total_area)
+
+
 def evaluate_placement(graph: Graph, x: torch.Tensor, net_ptr=None, pin_cell=None,
                        stream=None) -> dict:
     """Per-column smoothness S (eq. smoothness / wire_eq), squared norm,

@@ -390,8 +390,41 @@ def pin_exact_filter(lib):
     g.close()
 
 
+def pin_bin_density(lib):
+    """Bin density (eq. density_eq): hand-computed overlaps of a 2 x 1 cell
+    on a 4 x 4 grid; the densities of a placement inside the region sum to the
+    total cell area; a brute-force sampled overlap on random inputs."""
+    d = O.bin_density(np.array([[1.0, 1.5]]), 2.0, 1.0, (0, 0, 4, 4), 4, 4, lib=lib)
+    exp = np.zeros((4, 4))
+    # x in [0, 2], y in [1, 2]: bins (0, 1) and (1, 1) fully covered
+    exp[1, 0] = exp[1, 1] = 1.0
+    assert np.array_equal(d, exp), d
+    d = O.bin_density(np.array([[1.5, 1.0]]), 1.0, 1.0, (0, 0, 4, 4), 4, 4, lib=lib)
+    exp = np.zeros((4, 4))
+    exp[0, 1] = exp[1, 1] = 0.5  # x in [1, 2], y in [0.5, 1.5]
+    assert np.allclose(d, exp), d
+    rng = np.random.default_rng(4)
+    x = rng.uniform(5, 95, size=(200, 2))
+    w = rng.uniform(0.5, 4.0, size=200)
+    h = rng.uniform(0.5, 4.0, size=200)
+    d = O.bin_density(x, w, h, (0, 0, 100, 100), 7, 5, lib=lib)
+    assert np.isclose(d.sum(), (w * h).sum(), rtol=1e-12)
+    # one cell against an analytic per-bin overlap computed independently
+    for v in range(5):
+        one = O.bin_density(x[v:v + 1], w[v], h[v], (0, 0, 100, 100), 7, 5, lib=lib)
+        xs = np.clip([x[v, 0] - w[v] / 2, x[v, 0] + w[v] / 2], 0, 100)
+        ys = np.clip([x[v, 1] - h[v] / 2, x[v, 1] + h[v] / 2], 0, 100)
+        ex = np.zeros((5, 7))
+        for j in range(5):
+            for i in range(7):
+                lx = max(0.0, min(xs[1], (i + 1) * 100 / 7) - max(xs[0], i * 100 / 7))
+                ly = max(0.0, min(ys[1], (j + 1) * 20) - max(ys[0], j * 20))
+                ex[j, i] = lx * ly
+        assert np.allclose(one, ex, rtol=1e-12, atol=1e-12)
+
+
 ALL_PINS = [pin_golden_two_cell, pin_clique_closed_form, pin_hand_built,
             pin_brute_force_structure, pin_spectral, pin_theorem1_fixed_point,
             pin_spectrum, pin_isolated_and_fixed, pin_star_schur,
             pin_generated_invariants, pin_invalid_input, pin_evaluate_hand,
-            pin_evaluate_dense, pin_exact_filter]
+            pin_evaluate_dense, pin_exact_filter, pin_bin_density]
