@@ -1,10 +1,12 @@
 // C ABI plumbing: errors, stream-ordered allocation, graph info/export/destroy.
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
 #include <map>
 #include <mutex>
 #include <unordered_map>
+#include <vector>
 
 #include "common.h"
 
@@ -152,6 +154,67 @@ void pool_stats(int64_t *held, int64_t *in_use) {
   std::lock_guard<std::mutex> lk(pl.m);
   if (held) *held = pl.bytes_held;
   if (in_use) *in_use = pl.bytes_in_use;
+}
+
+namespace {
+struct ReadbackPool {
+  std::mutex m;
+  std::map<int, std::vector<Readback>> free;  // per device
+};
+ReadbackPool &readback_pool() {
+  static ReadbackPool *p = new ReadbackPool();
+  return *p;
+}
+}  // namespace
+
+gift_status readback_acquire(Readback *r) {
+  int dev = 0;
+  GIFT_HIP(hipGetDevice(&dev));
+  ReadbackPool &pl = readback_pool();
+  {
+    std::lock_guard<std::mutex> lk(pl.m);
+    auto &fl = pl.free[dev];
+    if (!fl.empty()) {
+      *r = fl.back();
+      fl.pop_back();
+      return GIFT_OK;
+    }
+  }
+  Readback n{nullptr, nullptr, nullptr, dev};
+  GIFT_HIP(hipHostMalloc(reinterpret_cast<void **>(&n.host), kReadbackSlots * sizeof(int64_t),
+                         hipHostMallocCoherent | hipHostMallocPortable));
+  hipError_t e = hipHostGetDevicePointer(reinterpret_cast<void **>(&n.dev), n.host, 0);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&n.done, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    (void)hipHostFree(n.host);
+    (void)hipGetLastError();
+    return set_error(GIFT_EDEVICE, "readback event: %s", hipGetErrorString(e));
+  }
+  *r = n;
+  return GIFT_OK;
+}
+
+void readback_release(const Readback &r) {
+  if (!r.host) return;
+  ReadbackPool &pl = readback_pool();
+  std::lock_guard<std::mutex> lk(pl.m);
+  pl.free[r.device].push_back(r);
+}
+
+gift_status readback_wait(const Readback &r, hipStream_t st) {
+  GIFT_HIP(hipEventRecord(r.done, st));
+  const auto t0 = std::chrono::steady_clock::now();
+  for (;;) {
+    const hipError_t q = hipEventQuery(r.done);
+    if (q == hipSuccess) return GIFT_OK;
+    if (q != hipErrorNotReady) {
+      (void)hipGetLastError();
+      return set_error(GIFT_EDEVICE, "readback: %s", hipGetErrorString(q));
+    }
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(300)) break;
+  }
+  GIFT_HIP(hipEventSynchronize(r.done));
+  return GIFT_OK;
 }
 
 const SigmaBlock *find_sigma(const gift_graph *g, double sigma) {

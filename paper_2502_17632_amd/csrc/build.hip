@@ -765,6 +765,7 @@ gift_status prepare_sigma(gift_graph *g, double sigma, hipStream_t st) {
 namespace {
 
 constexpr int kMaxReadback = 8;
+static_assert(kMaxReadback <= kReadbackSlots, "readback slots");
 
 // Copies int64 scalars from device memory into one small block so the host
 // reads them with a single transfer.
@@ -775,21 +776,26 @@ __global__ void k_gather_i64(ReadbackPtrs src, int n, int64_t *dst) {
   if (threadIdx.x < n) dst[threadIdx.x] = *src.p[threadIdx.x];
 }
 
-// Reads `n` device int64 scalars with one launch, one copy and one sync.
-gift_status read_scalars(Scratch &sc, hipStream_t st, const int64_t *const *ptrs, int n,
-                         int64_t *out) {
-  int64_t *dev = nullptr;
-  GIFT_TRY(sc.get(&dev, kMaxReadback, "readback"));
+// Reads `n` device int64 scalars with one launch and one wait: the kernel
+// writes them straight into a pinned host slot.  A slot whose wait failed is
+// not returned to the pool (its kernel may still write it).
+gift_status read_scalars(hipStream_t st, const int64_t *const *ptrs, int n, int64_t *out) {
+  Readback rb{};
+  GIFT_TRY(readback_acquire(&rb));
   ReadbackPtrs rp{};
   for (int i = 0; i < n; ++i) rp.p[i] = ptrs[i];
-  k_gather_i64<<<1, 64, 0, st>>>(rp, n, dev);
-  GIFT_TRY(check_launch("k_gather_i64"));
-  GIFT_HIP(hipMemcpyAsync(out, dev, n * 8, hipMemcpyDeviceToHost, st));
-  GIFT_HIP(hipStreamSynchronize(st));
+  k_gather_i64<<<1, 64, 0, st>>>(rp, n, rb.dev);
+  gift_status s = check_launch("k_gather_i64");
+  if (s != GIFT_OK) {
+    readback_release(rb);
+    return s;
+  }
+  GIFT_TRY(readback_wait(rb, st));
+  const volatile int64_t *h = rb.host;
+  for (int i = 0; i < n; ++i) out[i] = h[i];
+  readback_release(rb);
   return GIFT_OK;
 }
-
-__global__ void k_flag_to_i64(const uint32_t *flag, int64_t *out) { *out = *flag; }
 
 gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) {
   const int64_t N = d->num_cells, E = d->num_nets;
@@ -814,19 +820,17 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
     return set_error(GIFT_EUNSUPPORTED, "netlist too large (cells+nets %lld)",
                      (long long)(N + E));
 
-  uint32_t *flag = nullptr;
+  // error flags: the low word of a zeroed 64-bit word (read back as int64)
   int64_t *flag64 = nullptr;
-  GIFT_TRY(sc.get(&flag, 1, "flag"));
-  GIFT_TRY(sc.get(&flag64, 1, "flag copy"));
-  GIFT_HIP(hipMemsetAsync(flag, 0, 4, st));
+  GIFT_TRY(sc.get(&flag64, 1, "flag"));
+  GIFT_HIP(hipMemsetAsync(flag64, 0, 8, st));
+  uint32_t *flag = reinterpret_cast<uint32_t *>(flag64);
 
   // 0. check net_ptr and tile the nets, then read the flag, the pin count
   //    and the tile count back together; nothing reads pins before the check
   //    passed (tiling reads net_ptr only and stays in bounds for any values)
   k_check_netptr<<<grid_for(E + 1), kBlock, 0, st>>>(net_ptr, E, flag);
   GIFT_TRY(check_launch("k_check_netptr"));
-  k_flag_to_i64<<<1, 1, 0, st>>>(flag, flag64);
-  GIFT_TRY(check_launch("k_flag_to_i64"));
   int32_t *net_tiles = nullptr;
   int64_t *net_tile_counts = nullptr;
   GIFT_TRY(sc.get(&net_tiles, E + 2, "net tiles"));
@@ -835,7 +839,7 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
   int64_t h0[3] = {0, 0, 0};
   {
     const int64_t *ptrs[3] = {flag64, net_ptr + E, net_tile_counts};
-    GIFT_TRY(read_scalars(sc, st, ptrs, 3, h0));
+    GIFT_TRY(read_scalars(st, ptrs, 3, h0));
   }
   if (h0[0] & kFlagBadNetPtr)
     return set_error(GIFT_EINVAL, "net_ptr must start at 0, end at the pin count and not decrease");
@@ -874,7 +878,7 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
                                              wnet, bmax);
   GIFT_TRY(check_launch("k_classify"));
   k_max_reduce<<<1, kBlock, 0, st>>>(bmax, grid_for(E), mmax);
-  GIFT_TRY(check_launch("k_classify"));
+  GIFT_TRY(check_launch("k_max_reduce"));
   GIFT_TRY(scan_i32_to_i64(is_star, vrank, E, st));
   k_virtual_map<<<grid_for(E), kBlock, 0, st>>>(is_star, vrank, E, virt_net);
   GIFT_TRY(check_launch("k_virtual_map"));
@@ -893,14 +897,12 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
   GIFT_TRY(check_launch("k_count"));
   GIFT_TRY(scan_i32_to_i64(cnt, zoff, N, st));
   GIFT_TRY(build_tiles64(zoff, N, N, kBuildTiles, st, row_tiles, row_tile_counts));
-  k_flag_to_i64<<<1, 1, 0, st>>>(flag, flag64);
-  GIFT_TRY(check_launch("k_flag_to_i64"));
 
   // sizes back to the host: flag, V, Z, row tiles
   int64_t h1[5] = {0, 0, 0, 0, 0};
   {
     const int64_t *ptrs[5] = {flag64, vrank + E, zoff + N, row_tile_counts, mmax};
-    GIFT_TRY(read_scalars(sc, st, ptrs, 5, h1));
+    GIFT_TRY(read_scalars(st, ptrs, 5, h1));
   }
   if (h1[0] & kFlagBadPin) return set_error(GIFT_EINVAL, "a pin names a cell outside [0, num_cells)");
   const int64_t V = h1[1], Z = h1[2], num_row_tiles = h1[3], R = N + V;
@@ -949,7 +951,7 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
     ptrs[0] = rp64 + R;
     ptrs[1] = rp64 + N;
     for (int i = 0; i < 2 * kTileClasses; ++i) ptrs[2 + i] = tile_counts + i;
-    GIFT_TRY(read_scalars(sc, st, ptrs, 2 + 2 * kTileClasses, h2));
+    GIFT_TRY(read_scalars(st, ptrs, 2 + 2 * kTileClasses, h2));
   }
   const int64_t nnz = h2[0];
   if (nnz >= (int64_t(1) << 31))

@@ -81,6 +81,24 @@ void dev_free(void *p, hipStream_t s);
 gift_status release_cached(int dev);
 void pool_stats(int64_t *held, int64_t *in_use);
 
+// Host readback of a few device scalars without a copy: a slot of
+// kReadbackSlots int64 values in pinned, host-coherent memory that a kernel
+// writes directly, and an event recorded after that kernel.  Slots come from
+// a per-device pool (allocated once, kept for the life of the process) and
+// are returned with readback_release.
+constexpr int kReadbackSlots = 16;
+struct Readback {
+  int64_t *host;  // kReadbackSlots values, read by the host
+  int64_t *dev;   // the same memory as device code addresses it
+  hipEvent_t done;
+  int device;
+};
+gift_status readback_acquire(Readback *r);
+void readback_release(const Readback &r);
+// Records the event on `st` and waits for it: polls for a short while (the
+// usual case: the readback ends a short chain of kernels), then blocks.
+gift_status readback_wait(const Readback &r, hipStream_t st);
+
 // RAII holder for build/filter scratch, released in stream order.
 struct Scratch {
   hipStream_t stream;

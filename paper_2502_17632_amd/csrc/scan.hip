@@ -25,32 +25,54 @@ __global__ __launch_bounds__(kBlock) void k_tile_sums(const In *__restrict__ in,
 }
 
 // out[i] = offs[tile] + exclusive prefix within the tile; the last tile also
-// writes out[n] (the grand total).
+// writes out[n] (the grand total).  Each wave scans a contiguous quarter of
+// the tile, 64 consecutive elements per step (coalesced loads and stores),
+// carrying its running sum between steps; the waves' totals are combined
+// once through LDS.
 template <typename In>
 __global__ __launch_bounds__(kBlock) void k_tile_scan(const In *__restrict__ in, int64_t n,
                                                       const int64_t *__restrict__ offs,
                                                       int64_t *__restrict__ out) {
-  __shared__ int64_t tmp[kBlock / kWave];
-  int64_t base = static_cast<int64_t>(blockIdx.x) * kTile + static_cast<int64_t>(threadIdx.x) * kItems;
+  constexpr int kWaves = kBlock / kWave;
+  constexpr int64_t kPerWave = kTile / kWaves;
+  __shared__ int64_t tmp[kWaves];
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int64_t wbase = static_cast<int64_t>(blockIdx.x) * kTile + wid * kPerWave;
   int64_t v[kItems];
-  int64_t mine = 0;
 #pragma unroll
   for (int k = 0; k < kItems; ++k) {
-    int64_t i = base + k;
+    const int64_t i = wbase + k * kWave + lane;
     v[k] = i < n ? static_cast<int64_t>(in[i]) : 0;
-    mine += v[k];
   }
-  int64_t total;
-  int64_t run = block_excl_scan<int64_t>(mine, &total, tmp);
-  int64_t off = offs ? offs[blockIdx.x] : 0;
-  run += off;
+  int64_t carry = 0;
 #pragma unroll
   for (int k = 0; k < kItems; ++k) {
-    int64_t i = base + k;
-    if (i < n) out[i] = run;
-    run += v[k];
+    int64_t x = v[k];
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const int64_t y = __shfl_up(x, off, kWave);
+      if (lane >= off) x += y;
+    }
+    const int64_t incl = carry + x;
+    v[k] = incl - v[k];  // exclusive prefix within the wave's quarter
+    carry = __shfl(incl, kWave - 1, kWave);
   }
-  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = off + total;
+  if (lane == 0) tmp[wid] = carry;
+  __syncthreads();
+  int64_t before = 0, all = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) {
+    before += w < wid ? tmp[w] : 0;
+    all += tmp[w];
+  }
+  const int64_t off = (offs ? offs[blockIdx.x] : 0) + before;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) {
+    const int64_t i = wbase + k * kWave + lane;
+    if (i < n) out[i] = off + v[k];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0)
+    out[n] = (offs ? offs[blockIdx.x] : 0) + all;
 }
 
 template <typename In>
