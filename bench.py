@@ -407,6 +407,14 @@ def main():
             dens[name] = {"max_over_bin_area": round(float(d.max()) / (W.DIE / 512) ** 2, 3),
                           "overflow_at_1": round(gift.density_overflow(
                               d, box, 1.0, float(nl.num_cells)), 5)}
+        for _ in range(2):
+            gift.bin_density(y, box, 512, 512, w0=1.0, h0=1.0)
+        ev0.record()
+        for _ in range(5):
+            gift.bin_density(y, box, 512, 512, w0=1.0, h0=1.0)
+        ev1.record()
+        torch.cuda.synchronize()
+        dens["ms"] = round(ev0.elapsed_time(ev1) / 5, 4)
         out["bin_density_512"] = dens
         out["placement_metrics"] = {
             "initial": {k: [round(float(v), 6) for v in m0[k]] for k in m0},
