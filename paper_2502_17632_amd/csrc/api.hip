@@ -217,6 +217,52 @@ gift_status readback_wait(const Readback &r, hipStream_t st) {
   return GIFT_OK;
 }
 
+namespace {
+struct SidePool {
+  std::mutex m;
+  std::map<int, std::vector<SideStream>> free;  // per device
+};
+SidePool &side_pool() {
+  static SidePool *p = new SidePool();
+  return *p;
+}
+}  // namespace
+
+gift_status side_stream_acquire(SideStream *r) {
+  int dev = 0;
+  GIFT_HIP(hipGetDevice(&dev));
+  SidePool &pl = side_pool();
+  {
+    std::lock_guard<std::mutex> lk(pl.m);
+    auto &fl = pl.free[dev];
+    if (!fl.empty()) {
+      *r = fl.back();
+      fl.pop_back();
+      return GIFT_OK;
+    }
+  }
+  SideStream n{nullptr, nullptr, nullptr, dev};
+  hipError_t e = hipStreamCreateWithFlags(&n.stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&n.ready, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&n.done, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    if (n.done) (void)hipEventDestroy(n.done);
+    if (n.ready) (void)hipEventDestroy(n.ready);
+    if (n.stream) (void)hipStreamDestroy(n.stream);
+    (void)hipGetLastError();
+    return set_error(GIFT_EDEVICE, "side stream: %s", hipGetErrorString(e));
+  }
+  *r = n;
+  return GIFT_OK;
+}
+
+void side_stream_release(const SideStream &r) {
+  if (!r.stream) return;
+  SidePool &pl = side_pool();
+  std::lock_guard<std::mutex> lk(pl.m);
+  pl.free[r.device].push_back(r);
+}
+
 const SigmaBlock *find_sigma(const gift_graph *g, double sigma) {
   for (const SigmaBlock &b : g->sig)
     if (b.sigma == sigma) return &b;

@@ -259,11 +259,13 @@ __global__ __launch_bounds__(kBlock) void k_net_tiles(NetArgs a) {
 // ---------------------------------------------------------------------------
 // 2. classify nets
 // ---------------------------------------------------------------------------
-// Per net: star or clique, weight; and the largest net size of the block
-// into bmax[blockIdx.x].
+// Per net: star or clique, weight, the star code (star ? 1 | M << 32 : 0;
+// its exclusive scan gives every star net its virtual row and the number of
+// star entries before it); and the largest net size of the block into
+// bmax[blockIdx.x].
 __global__ __launch_bounds__(kBlock) void k_classify(const int32_t *M, int64_t E, int64_t T,
                                                      int model, int32_t *is_star, double *wnet,
-                                                     int32_t *bmax) {
+                                                     int64_t *star_code, int32_t *bmax) {
   __shared__ int32_t red[kBlock];
   int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   int32_t mine = 0;
@@ -271,6 +273,7 @@ __global__ __launch_bounds__(kBlock) void k_classify(const int32_t *M, int64_t E
     int64_t m = M[e];
     bool star = m >= 2 && T > 0 && m > T;
     is_star[e] = star ? 1 : 0;
+    star_code[e] = star ? (1 | (m << 32)) : 0;
     wnet[e] = m < 2 ? 0.0 : (star ? star_weight(m, model) : clique_weight(m, model));
     mine = static_cast<int32_t>(m);
   }
@@ -282,6 +285,11 @@ __global__ __launch_bounds__(kBlock) void k_classify(const int32_t *M, int64_t E
     __syncthreads();
   }
   if (threadIdx.x == 0) bmax[blockIdx.x] = red[0];
+}
+
+// Virtual row of star net e from the scanned star codes.
+__device__ __forceinline__ int64_t virtual_rank(const int64_t *vscan, int64_t e) {
+  return vscan[e] & 0xffffffff;
 }
 
 // *out = max of v[0..n), one block.
@@ -300,10 +308,10 @@ __global__ __launch_bounds__(kBlock) void k_max_reduce(const int32_t *v, int64_t
   if (threadIdx.x == 0) *out = red[0];
 }
 
-__global__ void k_virtual_map(const int32_t *is_star, const int64_t *vrank, int64_t E,
+__global__ void k_virtual_map(const int32_t *is_star, const int64_t *vscan, int64_t E,
                               int32_t *virt_net) {
   int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e < E && is_star[e]) virt_net[vrank[e]] = static_cast<int32_t>(e);
+  if (e < E && is_star[e]) virt_net[virtual_rank(vscan, e)] = static_cast<int32_t>(e);
 }
 
 // ---------------------------------------------------------------------------
@@ -312,7 +320,7 @@ __global__ void k_virtual_map(const int32_t *is_star, const int64_t *vrank, int6
 struct EmitArgs {
   const int64_t *net_ptr;
   const int32_t *ucell, *pin_net, *M, *is_star;
-  const int64_t *vrank;
+  const int64_t *vscan;  // scanned star codes
   int64_t E, P, N;
   KeyLayout L;
 };
@@ -359,7 +367,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(EmitArgs a, const int64_t *zoff
       const bool star = a.is_star[e] != 0;
       n = star ? 1 : static_cast<int32_t>(m - 1);
       dst[threadIdx.x] = zoff[a.ucell[p]] + slot[p];
-      lo_of[threadIdx.x] = star ? a.N + a.vrank[e] : lo;
+      lo_of[threadIdx.x] = star ? a.N + virtual_rank(a.vscan, e) : lo;
       net_of[threadIdx.x] = e;
       self_of[threadIdx.x] = star ? -1 : static_cast<int32_t>(i);
       m_of[threadIdx.x] = static_cast<int32_t>(m);
@@ -864,10 +872,11 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
 
   // 2. classify
   int32_t *is_star = nullptr, *virt_net = nullptr;
-  int64_t *vrank = nullptr;
+  int64_t *star_code = nullptr, *vscan = nullptr;
   double *wnet = nullptr;
   GIFT_TRY(sc.get(&is_star, E, "star flags"));
-  GIFT_TRY(sc.get(&vrank, E + 1, "virtual ranks"));
+  GIFT_TRY(sc.get(&star_code, E, "star codes"));
+  GIFT_TRY(sc.get(&vscan, E + 1, "virtual ranks and star entry offsets"));
   GIFT_TRY(sc.get(&wnet, E, "net weights"));
   GIFT_TRY(sc.get(&virt_net, E, "virtual nets"));
   int64_t *mmax = nullptr;
@@ -875,12 +884,12 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
   GIFT_TRY(sc.get(&mmax, 1, "largest net"));
   GIFT_TRY(sc.get(&bmax, grid_for(E), "largest net per block"));
   k_classify<<<grid_for(E), kBlock, 0, st>>>(M, E, d->star_threshold, d->weight_model, is_star,
-                                             wnet, bmax);
+                                             wnet, star_code, bmax);
   GIFT_TRY(check_launch("k_classify"));
   k_max_reduce<<<1, kBlock, 0, st>>>(bmax, grid_for(E), mmax);
   GIFT_TRY(check_launch("k_max_reduce"));
-  GIFT_TRY(scan_i32_to_i64(is_star, vrank, E, st));
-  k_virtual_map<<<grid_for(E), kBlock, 0, st>>>(is_star, vrank, E, virt_net);
+  GIFT_TRY(scan_i64(star_code, vscan, E, st));
+  k_virtual_map<<<grid_for(E), kBlock, 0, st>>>(is_star, vscan, E, virt_net);
   GIFT_TRY(check_launch("k_virtual_map"));
 
   // 3. entries per cell row, row tiles over the pre-merge slices
@@ -892,27 +901,39 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
   GIFT_TRY(sc.get(&row_tiles, N + 2, "row tiles"));
   GIFT_TRY(sc.get(&row_tile_counts, 2, "row tile counts"));
   GIFT_HIP(hipMemsetAsync(cnt, 0, N * 4 + 4, st));
-  EmitArgs ea{net_ptr, ucell, pin_net, M, is_star, vrank, E, P, N, KeyLayout{}};
+  EmitArgs ea{net_ptr, ucell, pin_net, M, is_star, vscan, E, P, N, KeyLayout{}};
   k_count<<<grid_for(P), kBlock, 0, st>>>(ea, cnt, slot);
   GIFT_TRY(check_launch("k_count"));
   GIFT_TRY(scan_i32_to_i64(cnt, zoff, N, st));
   GIFT_TRY(build_tiles64(zoff, N, N, kBuildTiles, st, row_tiles, row_tile_counts));
 
-  // sizes back to the host: flag, V, Z, row tiles
+  // sizes back to the host: flag, {V, star entries}, Z, row tiles, largest
+  // net
   int64_t h1[5] = {0, 0, 0, 0, 0};
   {
-    const int64_t *ptrs[5] = {flag64, vrank + E, zoff + N, row_tile_counts, mmax};
+    const int64_t *ptrs[5] = {flag64, vscan + E, zoff + N, row_tile_counts, mmax};
     GIFT_TRY(read_scalars(st, ptrs, 5, h1));
   }
   if (h1[0] & kFlagBadPin) return set_error(GIFT_EINVAL, "a pin names a cell outside [0, num_cells)");
-  const int64_t V = h1[1], Z = h1[2], num_row_tiles = h1[3], R = N + V;
+  const int64_t V = h1[1] & 0xffffffff, star_entries = h1[1] >> 32;
+  const int64_t Z = h1[2], num_row_tiles = h1[3], R = N + V;
   const KeyLayout L = key_layout(R > 0 ? R - 1 : 0, E > 0 ? E - 1 : 0, h1[4]);
   ea.L = L;
   if (R >= (int64_t(1) << 31))
     return set_error(GIFT_EUNSUPPORTED, "too many rows (%lld)", (long long)R);
+  // merging only removes entries: Z + star_entries bounds the stored count,
+  // so the CSR is allocated now and its exact size read back at the end
+  const int64_t cap = Z + star_entries;
+  if (cap >= (int64_t(1) << 31))
+    return set_error(GIFT_EUNSUPPORTED, "too many stored entries (up to %lld)", (long long)cap);
   g->num_cells = N;
   g->num_virtual = V;
   g->num_rows = R;
+  GIFT_TRY(dev_alloc(reinterpret_cast<void **>(&g->row_ptr), (R + 1) * 4, st, "row_ptr"));
+  GIFT_TRY(dev_alloc(reinterpret_cast<void **>(&g->col), cap * 4, st, "col"));
+  GIFT_TRY(dev_alloc(reinterpret_cast<void **>(&g->w), cap * 8, st, "weights"));
+  GIFT_TRY(dev_alloc(reinterpret_cast<void **>(&g->deg), R * 8, st, "degrees"));
+  g->bytes = (R + 1) * 4 + cap * 12 + R * 8;
 
   // 3b. emit
   uint64_t *zkey = nullptr, *zsort = nullptr;
@@ -934,37 +955,62 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
     GIFT_TRY(check_launch("k_virtual_counts"));
   }
 
-  // 5. row_ptr and the SpMM row tiles of every class
+  // 5. row_ptr; the SpMM row tiles of every class on a side stream while
+  //    this stream merges
   int64_t *rp64 = nullptr;
   GIFT_TRY(sc.get(&rp64, R + 1, "row offsets (64-bit)"));
   GIFT_TRY(scan_i32_to_i64(ucnt, rp64, R, st));
+  k_row_ptr32<<<grid_for(R + 1), kBlock, 0, st>>>(rp64, R, g->row_ptr);
+  GIFT_TRY(check_launch("k_row_ptr32"));
   int32_t *tstart[kTileClasses];
   int64_t *tile_counts = nullptr;
   GIFT_TRY(sc.get(&tile_counts, 2 * kTileClasses, "tile counts"));
-  for (int c = 0; c < kTileClasses; ++c) {
-    GIFT_TRY(sc.get(&tstart[c], R + 2, "tile starts"));
-    GIFT_TRY(build_tiles64(rp64, R, N, kSpmmTiles[c], st, tstart[c], tile_counts + 2 * c));
+  for (int c = 0; c < kTileClasses; ++c) GIFT_TRY(sc.get(&tstart[c], R + 2, "tile starts"));
+  SideStream side{};
+  GIFT_TRY(side_stream_acquire(&side));
+  gift_status ss = GIFT_OK;
+  // everything the side stream reads or writes was allocated above, so it
+  // is ordered after all earlier users of those blocks by this event
+  if (hipEventRecord(side.ready, st) != hipSuccess ||
+      hipStreamWaitEvent(side.stream, side.ready, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    ss = set_error(GIFT_EDEVICE, "side stream ordering failed");
   }
+  // 6. merge the cell rows here; the star rows (a disjoint part of the CSR)
+  //    on the side stream
+  if (ss == GIFT_OK && V > 0) {
+    k_star_rows<<<grid_for(V * kWave), kBlock, 0, side.stream>>>(
+        virt_net, net_ptr, M, ucell, wnet, g->row_ptr, N, V, g->col, g->w, g->deg);
+    ss = check_launch("k_star_rows");
+  }
+  for (int c = 0; c < kTileClasses && ss == GIFT_OK; ++c)
+    ss = build_tiles64(rp64, R, N, kSpmmTiles[c], side.stream, tstart[c], tile_counts + 2 * c);
+  if (ss == GIFT_OK && num_row_tiles > 0) {
+    MergeArgs ma{zoff, zsort, wnet, g->row_ptr, row_tiles, g->col, g->w, g->deg,
+                 L, N, d->weight_model};
+    k_row_merge_tiles<<<static_cast<unsigned>(num_row_tiles), kBlock, 0, st>>>(ma);
+    ss = check_launch("k_row_merge_tiles");
+  }
+
+  // CSR and tile counts, read from the side stream while the merge runs
   int64_t h2[2 + 2 * kTileClasses] = {};
-  {
+  if (ss == GIFT_OK) {
     const int64_t *ptrs[2 + 2 * kTileClasses];
     ptrs[0] = rp64 + R;
     ptrs[1] = rp64 + N;
     for (int i = 0; i < 2 * kTileClasses; ++i) ptrs[2 + i] = tile_counts + i;
-    GIFT_TRY(read_scalars(st, ptrs, 2 + 2 * kTileClasses, h2));
+    ss = read_scalars(side.stream, ptrs, 2 + 2 * kTileClasses, h2);
   }
-  const int64_t nnz = h2[0];
-  if (nnz >= (int64_t(1) << 31))
-    return set_error(GIFT_EUNSUPPORTED, "too many stored entries (%lld)", (long long)nnz);
-  g->nnz = nnz;
+  // the side stream is idle here unless a call above failed: then wait for
+  // it before its scratch and the stream go back to their pools
+  if (ss != GIFT_OK) (void)hipStreamSynchronize(side.stream);
+  side_stream_release(side);
+  GIFT_TRY(ss);
+  g->nnz = h2[0];
   g->nnz_cells = h2[1];
-  GIFT_TRY(dev_alloc(reinterpret_cast<void **>(&g->row_ptr), (R + 1) * 4, st, "row_ptr"));
-  GIFT_TRY(dev_alloc(reinterpret_cast<void **>(&g->col), nnz * 4, st, "col"));
-  GIFT_TRY(dev_alloc(reinterpret_cast<void **>(&g->w), nnz * 8, st, "weights"));
-  GIFT_TRY(dev_alloc(reinterpret_cast<void **>(&g->deg), R * 8, st, "degrees"));
-  g->bytes = (R + 1) * 4 + nnz * 12 + R * 8;
-  k_row_ptr32<<<grid_for(R + 1), kBlock, 0, st>>>(rp64, R, g->row_ptr);
-  GIFT_TRY(check_launch("k_row_ptr32"));
+  // the side stream's work is complete (its readback returned), so this
+  // stream may read the tile starts and the star rows without further
+  // ordering
   for (int c = 0; c < kTileClasses; ++c) {
     g->num_tiles[c] = h2[2 + 2 * c];
     g->num_tiles_cells[c] = h2[3 + 2 * c];
@@ -972,19 +1018,6 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
                        (g->num_tiles[c] + 1) * sizeof(TileDesc), st, "row tiles"));
     g->bytes += (g->num_tiles[c] + 1) * static_cast<int64_t>(sizeof(TileDesc));
     GIFT_TRY(tile_descs(tstart[c], rp64, g->num_tiles[c], st, g->tiles[c]));
-  }
-
-  // 6. merge
-  if (num_row_tiles > 0) {
-    MergeArgs ma{zoff, zsort, wnet, g->row_ptr, row_tiles, g->col, g->w, g->deg,
-                 L, N, d->weight_model};
-    k_row_merge_tiles<<<static_cast<unsigned>(num_row_tiles), kBlock, 0, st>>>(ma);
-    GIFT_TRY(check_launch("k_row_merge_tiles"));
-  }
-  if (V > 0) {
-    k_star_rows<<<grid_for(V * kWave), kBlock, 0, st>>>(virt_net, net_ptr, M, ucell, wnet,
-                                                         g->row_ptr, N, V, g->col, g->w, g->deg);
-    GIFT_TRY(check_launch("k_star_rows"));
   }
 
   // 7. normalisation

@@ -99,6 +99,19 @@ void readback_release(const Readback &r);
 // usual case: the readback ends a short chain of kernels), then blocks.
 gift_status readback_wait(const Readback &r, hipStream_t st);
 
+// A second stream (default priority) with two events, for work a call runs
+// beside its caller's stream: `ready` is recorded on the caller's stream and
+// waited on by `stream`; `done` is free for the caller.  From a per-device
+// pool kept for the life of the process.
+struct SideStream {
+  hipStream_t stream;
+  hipEvent_t ready;
+  hipEvent_t done;
+  int device;
+};
+gift_status side_stream_acquire(SideStream *s);
+void side_stream_release(const SideStream &s);
+
 // RAII holder for build/filter scratch, released in stream order.
 struct Scratch {
   hipStream_t stream;
@@ -180,6 +193,7 @@ gift_status prepare_sigma(gift_graph *g, double sigma, hipStream_t s);
 
 // Exclusive prefix sum: out[0..n] with out[n] = total (int64 output).
 gift_status scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, hipStream_t s);
+gift_status scan_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t s);
 
 // Row tiles (see tiles.hip): a tile is a single row longer than long_row or
 // rows starting in one window of `entries` entries, at most `rows` rows.

@@ -99,4 +99,8 @@ gift_status scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, hipStrea
   return scan_impl<int32_t>(in, out, n, s);
 }
 
+gift_status scan_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t s) {
+  return scan_impl<int64_t>(in, out, n, s);
+}
+
 }  // namespace gift
