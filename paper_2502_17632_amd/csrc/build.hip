@@ -682,7 +682,9 @@ __global__ __launch_bounds__(kBlock) void k_sigma_values(const int32_t *row_ptr,
   __shared__ int32_t loff[TCL::kRows + 2];
   __shared__ uint16_t seg[TCL::kCap + 1];
   __shared__ double ls[TCL::kRows + 1];
-  const TileDesc td = tiles[blockIdx.x];
+  // each XCD takes a contiguous range of tiles, so the s_j of neighbouring
+  // rows that its tiles share stay in its L2
+  const TileDesc td = tiles[xcd_remap(blockIdx.x, gridDim.x)];
   const int64_t r0 = td.r0, r1 = td.r1, p0 = td.p0, p1 = td.p1;
   const int ns = static_cast<int>(r1 - r0);
   if (ns == 1 && p1 - p0 > TCL::kLong) {

@@ -346,14 +346,20 @@ __device__ __forceinline__ void gstore(T *p, int64_t i, const T &t) {
   for (int k = 0; k < GWord<T>::kWords; ++k) q[k] = w[k];
 }
 
-// Blocks are dispatched round-robin over the 8 XCDs.  Remap so that every XCD
-// works on one contiguous range of logical blocks (and so of rows): the signal
-// rows a block gathers are then mostly in its own XCD's L2.
+// Blocks are dispatched round-robin over the 8 XCDs.  Remap logical tiles so
+// that every XCD works on chunks of kXcdChunk consecutive tiles (and so of
+// rows), the chunks dealt round-robin to the XCDs: the signal rows a tile
+// gathers from its neighbourhood are then mostly in its own XCD's L2, while
+// a heavy region of the tile list (the star rows at its end) is still spread
+// over all XCDs.  Tiles past the last whole round of chunks keep their index.
+// A bijection on [0, n) for any n.
+constexpr uint32_t kXcds = 8;
+constexpr uint32_t kXcdChunk = 64;
 __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t n) {
-  const uint32_t kXcd = 8;
-  uint32_t x = b % kXcd, i = b / kXcd;
-  uint32_t q = n / kXcd, r = n % kXcd;
-  return x * q + (x < r ? x : r) + i;
+  const uint32_t full = n / (kXcds * kXcdChunk) * (kXcds * kXcdChunk);
+  if (b >= full) return b;
+  const uint32_t x = b % kXcds, i = b / kXcds;
+  return ((i / kXcdChunk) * kXcds + x) * kXcdChunk + (i % kXcdChunk);
 }
 
 inline unsigned grid_for(int64_t threads, int block = 256) {

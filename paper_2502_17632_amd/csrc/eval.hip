@@ -49,7 +49,8 @@ __global__ __launch_bounds__(kBlock) void k_eval_smooth(const TileDesc *tiles,
                                                         int32_t dt, const double *vx,
                                                         int32_t C, double *part) {
   __shared__ double red[kBlock];
-  const TileDesc td = gload(tiles, blockIdx.x);
+  const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x);
+  const TileDesc td = gload(tiles, tile);
   const gptr<const int32_t> rp = to_global(row_ptr), cl = to_global(col);
   const gptr<const double> wv = to_global(w), vxg = to_global(vx);
   for (int32_t q = 0; q < C; ++q) {
@@ -72,7 +73,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_smooth(const TileDesc *tiles,
       if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
       __syncthreads();
     }
-    if (threadIdx.x == 0) part[static_cast<int64_t>(blockIdx.x) * 2 * C + q] = red[0];
+    if (threadIdx.x == 0) part[static_cast<int64_t>(tile) * 2 * C + q] = red[0];
     __syncthreads();
     red[threadIdx.x] = n2;
     __syncthreads();
@@ -80,7 +81,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_smooth(const TileDesc *tiles,
       if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
       __syncthreads();
     }
-    if (threadIdx.x == 0) part[static_cast<int64_t>(blockIdx.x) * 2 * C + C + q] = red[0];
+    if (threadIdx.x == 0) part[static_cast<int64_t>(tile) * 2 * C + C + q] = red[0];
     __syncthreads();
   }
 }

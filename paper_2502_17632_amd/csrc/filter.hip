@@ -333,8 +333,9 @@ __global__ __launch_bounds__(kBlock) void k_spmm(LaunchArgs l, const void *xin, 
 template <int D, int C, bool kBatch>
 __global__ __launch_bounds__(kBlock) void k_prep(LaunchArgs l, int32_t in_dtype, int32_t col0,
                                                  void *x0v) {
-  const TileDesc td = gload(l.tiles, blockIdx.x);
-  const GraphDev gd = graph_of<kBatch>(l, blockIdx.x);
+  const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x);
+  const TileDesc td = gload(l.tiles, tile);
+  const GraphDev gd = graph_of<kBatch>(l, tile);
   const GraphIO &io = gd.io;
   const gptr<typename Store<D>::T> x0 =
       to_global(static_cast<typename Store<D>::T *>(x0v)) + gd.row_off * C;
