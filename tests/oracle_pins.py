@@ -423,8 +423,94 @@ def pin_bin_density(lib):
         assert np.allclose(one, ex, rtol=1e-12, atol=1e-12)
 
 
+def _path_netlist(cells):
+    """2-pin nets joining consecutive entries of `cells` (a path graph)."""
+    pins = []
+    for a, b in zip(cells[:-1], cells[1:]):
+        pins += [b, a] if (a + b) % 2 else [a, b]
+    net_ptr = np.arange(0, len(pins) + 1, 2, dtype=np.int64)
+    return net_ptr, np.array(pins, dtype=np.int32)
+
+
+def pin_eigen_path(lib, eig=None):
+    """Eigenvector placement (eq. ideal_filter on L = D - A, Section 2.1): a
+    chain of n cells joined by 2-pin nets (weight 1) is the path graph, whose
+    Laplacian has eigenvalues 2 - 2 cos(pi k / n) and eigenvectors
+    cos(pi k (i + 1/2) / n), k = 0..n-1."""
+    from oracle import eigen as E
+    eig = eig or E
+    for n in (5, 9, 16):
+        net_ptr, pins = _path_netlist(list(range(n)))
+        lam, vec, labels, g, _ = eig.eigen_placement(n, net_ptr, pins)
+        k = np.array([1.0, 2.0])
+        assert np.allclose(lam, 2 - 2 * np.cos(np.pi * k / n), rtol=1e-12, atol=1e-13), lam
+        assert np.all(labels == 0) and g == 0
+        for q in range(2):
+            u = np.cos(np.pi * (q + 1) * (np.arange(n) + 0.5) / n)
+            u /= np.linalg.norm(u)
+            assert min(np.linalg.norm(vec[:, q] - u), np.linalg.norm(vec[:, q] + u)) < 1e-10
+            assert vec[int(np.argmax(np.abs(vec[:, q]))), q] > 0
+
+
+def pin_eigen_complete(lib, eig=None):
+    """One net of M cells is the complete graph with weight w(M): eigenvalues
+    0 and M w(M) (M - 1 times), for both weight models."""
+    from oracle import eigen as E
+    eig = eig or E
+    m = 6
+    net_ptr = np.array([0, m], dtype=np.int64)
+    pins = np.array([3, 0, 5, 1, 4, 2], dtype=np.int32)
+    for model, wm in ((0, 1.0 / (m - 1)), (1, 2.0 / m)):
+        lam, vec, labels, g, full = eig.eigen_placement(m, net_ptr, pins, model)
+        assert np.allclose(full, [0.0] + [m * wm] * (m - 1), rtol=1e-12, atol=1e-12), full
+        # the eigenvectors are orthonormal and orthogonal to the constant
+        assert np.allclose(vec.T @ vec, np.eye(2), atol=1e-12)
+        assert np.allclose(vec.sum(axis=0), 0.0, atol=1e-12)
+
+
+def pin_eigen_components(lib, eig=None):
+    """Components and the giant component: two disjoint paths (cells 0..4 and
+    10..17), isolated cells and a separate pair; labels are the smallest cell
+    of each component (checked against scipy's connected components), the
+    8-cell path is the giant one, cells outside it get 0, and its eigenvalues
+    are those of the 8-path."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import connected_components
+    from oracle import eigen as E
+    eig = eig or E
+    n = 22
+    p1, q1 = _path_netlist([4, 2, 0, 1, 3])
+    p2, q2 = _path_netlist(list(range(10, 18)))
+    pins = np.concatenate([q1, q2, np.array([19, 20, 7, 7], dtype=np.int32)])
+    net_ptr = np.arange(0, len(pins) + 1, 2, dtype=np.int64)
+    lam, vec, labels, g, _ = eig.eigen_placement(n, net_ptr, pins)
+    assert g == 10 and np.count_nonzero(labels == g) == 8
+    assert np.all(vec[labels != g] == 0.0)
+    assert np.allclose(lam, 2 - 2 * np.cos(np.pi * np.array([1.0, 2.0]) / 8), rtol=1e-12)
+    rng = np.random.default_rng(12)
+    for trial in range(4):
+        nc = int(rng.integers(20, 60))
+        net_ptr, pins = _random_netlist(rng, nc, int(rng.integers(5, 25)), 5)
+        lab = eig.components(nc, net_ptr, pins)
+        rows, cols = [], []
+        for e in range(len(net_ptr) - 1):
+            cs = pins[net_ptr[e]:net_ptr[e + 1]]
+            for c in cs[1:]:
+                rows.append(cs[0])
+                cols.append(c)
+        adj = sp.coo_matrix((np.ones(len(rows)), (rows, cols)), shape=(nc, nc))
+        k, ref = connected_components(adj, directed=False)
+        for comp in range(k):
+            members = np.flatnonzero(ref == comp)
+            assert np.all(lab[members] == members.min())
+
+
 ALL_PINS = [pin_golden_two_cell, pin_clique_closed_form, pin_hand_built,
             pin_brute_force_structure, pin_spectral, pin_theorem1_fixed_point,
             pin_spectrum, pin_isolated_and_fixed, pin_star_schur,
             pin_generated_invariants, pin_invalid_input, pin_evaluate_hand,
             pin_evaluate_dense, pin_exact_filter, pin_bin_density]
+
+# the eigenvector-placement oracle is numpy (oracle/eigen.py); its pins take
+# the module to check, so mutants of it can be run through them
+EIGEN_PINS = [pin_eigen_path, pin_eigen_complete, pin_eigen_components]
