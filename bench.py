@@ -416,6 +416,17 @@ def main():
         torch.cuda.synchronize()
         dens["ms"] = round(ev0.elapsed_time(ev1) / 5, 4)
         out["bin_density_512"] = dens
+        # eigenvector placement [u_2, u_3] of the clique-model Laplacian, the
+        # paper's comparison baseline
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, einfo = gift.eigen_placement(g, tol=1e-8, max_iter=400)
+        e_ms = (time.perf_counter() - t0) * 1e3
+        out["eigen_placement"] = {
+            "tol": 1e-8, "lambda": [round(v, 9) for v in einfo["lambda"]],
+            "residual_over_bound": [v / einfo["spectral_bound"] for v in einfo["residual"]],
+            "iterations": einfo["iterations"], "converged": einfo["converged"],
+            "component_cells": einfo["component_cells"], "ms": round(e_ms, 2)}
         out["placement_metrics"] = {
             "initial": {k: [round(float(v), 6) for v in m0[k]] for k in m0},
             "filtered": {k: [round(float(v), 6) for v in m1[k]] for k in m1},

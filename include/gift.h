@@ -280,6 +280,54 @@ gift_status gift_evaluate_placement(const gift_graph *graph, const void *x, int3
                                     void *stream);
 
 /*
+ * gift_eigen_placement -- the eigenvector placement that Section 3.3.1
+ * analyses as the ideal low-pass filter (eq. ideal_filter): the placement
+ * [u_2, u_3], the eigenvectors of the second and third smallest eigenvalues
+ * of the graph Laplacian L = D - A (Section 2.1) of the clique net model.
+ *
+ * The graph's star nets are eliminated exactly (a star row at the mean of its
+ * cells turns the star into its clique), so the result does not depend on
+ * the star threshold.  Each connected component adds a zero eigenvalue, so
+ * the eigenvectors are those of the largest component (most cells; ties: the
+ * component with the smallest cell index) with its constant vector projected
+ * out; cells outside it get 0.  Each vector has unit norm and its
+ * largest-magnitude entry (first such row) positive.  Computed by
+ * Chebyshev-filtered subspace iteration on a block of 4 vectors in float64
+ * until both residuals ||L u - lambda u|| are at most tol * b (b = 2 max
+ * degree >= lambda_max) or max_iter iterations.  The component labels are
+ * found on the device (smallest row index of each component).
+ *
+ *   tol, max_iter  relative residual (> 0) and iteration cap (>= 1).
+ *   seed           start block (a hash of seed, row and column).
+ *   y_out          device float64 N x 2, leading dimension ld_out >= 2:
+ *                  u_2 in column 0, u_3 in column 1.
+ *   labels         device int32[num_rows] or NULL: every row's component
+ *                  label (cells and star rows).
+ *   result         host: eigenvalues, residuals, iterations, component.
+ *
+ * Synchronises `stream` (the host drives the iteration).  Errors: GIFT_EINVAL
+ * (NULL pointers, bad tol / max_iter / ld_out, fewer than 6 cells in the
+ * largest component), GIFT_EUNSUPPORTED (components not settled),
+ * GIFT_ENOMEM, GIFT_EDEVICE.  Not converging within max_iter is not an error:
+ * result->converged is 0.
+ */
+typedef struct {
+  double lambda[2];         /* lambda_2, lambda_3 */
+  double residual[2];       /* ||L u - lambda u|| of the unit eigenvectors */
+  double spectral_bound;    /* b = 2 max degree, the scale of tol */
+  int64_t component_label;  /* smallest cell index of the component used */
+  int64_t component_cells;  /* cells in that component */
+  int32_t iterations;       /* filtered subspace iterations */
+  int32_t sweeps;           /* sweeps of the component labelling */
+  int32_t converged;        /* 1 if both residuals <= tol * spectral_bound */
+  int32_t reserved;
+} gift_eigen_result;
+
+gift_status gift_eigen_placement(const gift_graph *graph, double tol, int32_t max_iter,
+                                 uint64_t seed, double *y_out, int64_t ld_out, int32_t *labels,
+                                 gift_eigen_result *result, void *stream);
+
+/*
  * gift_bin_density -- bin density of a placement (Section 2.2,
  * eq. density_eq): the region [xl, xh] x [yl, yh] is cut into nbx x nby equal
  * bins and

@@ -128,6 +128,15 @@ class ServerStats(C.Structure):
     ]
 
 
+class EigenResult(C.Structure):
+    _fields_ = [
+        ("lambda", C.c_double * 2), ("residual", C.c_double * 2),
+        ("spectral_bound", C.c_double), ("component_label", C.c_int64),
+        ("component_cells", C.c_int64), ("iterations", C.c_int32), ("sweeps", C.c_int32),
+        ("converged", C.c_int32), ("reserved", C.c_int32),
+    ]
+
+
 class GiftError(RuntimeError):
     def __init__(self, status: int, where: str, message: str):
         self.status = status
@@ -152,6 +161,9 @@ SIGNATURES = {
                                    C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double,
                                    C.c_double, C.c_double, C.c_int32, C.c_int32, C.c_void_p,
                                    C.c_void_p]),
+    "gift_eigen_placement": (C.c_int, [C.c_void_p, C.c_double, C.c_int32, C.c_uint64,
+                                       C.c_void_p, C.c_int64, C.c_void_p,
+                                       C.POINTER(EigenResult), C.c_void_p]),
     "gift_evaluate_placement": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int64,
                                           C.c_int32, C.c_void_p, C.c_void_p, C.c_int64,
                                           C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,

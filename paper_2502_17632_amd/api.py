@@ -207,6 +207,30 @@ def filter_exact(graph: Graph, sigma: float, x: torch.Tensor, *, tol: float = 1e
     return out, it.value
 
 
+def eigen_placement(graph: Graph, *, tol: float = 1e-10, max_iter: int = 1000,
+                    seed: int = 1, labels: bool = False, stream=None):
+    """Eigenvector placement [u_2, u_3] of the clique-model Laplacian on the
+    largest connected component (Section 3.3.1).  Returns (N x 2 float64 CUDA
+    tensor, info dict[, int32 labels of every graph row])."""
+    inf = graph.info()
+    n, r = inf["num_cells"], inf["num_rows"]
+    dev = torch.device("cuda", torch.cuda.current_device())
+    out = torch.empty((n, 2), dtype=torch.float64, device=dev)
+    lab = torch.empty(r, dtype=torch.int32, device=dev) if labels else None
+    res = L.EigenResult()
+    L.check(L.lib().gift_eigen_placement(graph.handle, float(tol), int(max_iter),
+                                         int(seed) & 0xFFFFFFFFFFFFFFFF, _ptr(out), 2,
+                                         _ptr(lab), C.byref(res), _stream_handle(stream)),
+            "gift_eigen_placement")
+    lam = getattr(res, "lambda")
+    info = {"lambda": [lam[0], lam[1]],
+            "residual": [res.residual[0], res.residual[1]],
+            "spectral_bound": res.spectral_bound, "component_label": res.component_label,
+            "component_cells": res.component_cells, "iterations": res.iterations,
+            "sweeps": res.sweeps, "converged": bool(res.converged)}
+    return (out, info, lab) if labels else (out, info)
+
+
 def bin_density(x: torch.Tensor, box: Sequence[float], nbx: int, nby: int, *,
                 widths: Optional[torch.Tensor] = None, heights: Optional[torch.Tensor] = None,
                 w0: float = 1.0, h0: float = 1.0, stream=None) -> torch.Tensor:

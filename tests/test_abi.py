@@ -46,7 +46,8 @@ def test_abi_version_and_status_strings():
 STRUCTS = {"gift_graph_desc": L.GraphDesc, "gift_term": L.Term, "gift_graph_info": L.GraphInfo,
            "gift_batch_io": L.BatchIO, "gift_batch_info": L.BatchInfo,
            "gift_server_config": L.ServerConfig, "gift_request": L.Request,
-           "gift_request_result": L.RequestResult, "gift_server_stats": L.ServerStats}
+           "gift_request_result": L.RequestResult, "gift_server_stats": L.ServerStats,
+           "gift_eigen_result": L.EigenResult}
 
 
 def c_layouts(tmp_path):
@@ -194,3 +195,12 @@ def test_evaluate_arguments_rejected_without_device_work():
     out = (C.c_double * 2)()
     assert lib.gift_evaluate_placement(None, None, 2, 2, 0, None, None, 0, 0, out, None, None,
                                        None) == L.GIFT_EINVAL
+
+
+def test_eigen_arguments_rejected_without_device_work():
+    lib = L.lib()
+    res = L.EigenResult()
+    y = (C.c_double * 16)()
+    assert lib.gift_eigen_placement(None, 1e-8, 10, 1, y, 2, None, C.byref(res),
+                                    None) == L.GIFT_EINVAL
+    assert lib.gift_eigen_placement(None, 1e-8, 10, 1, y, 2, None, None, None) == L.GIFT_EINVAL
