@@ -14,7 +14,7 @@
 // per row tile: all of a thread's loads are issued at once (col/values, the
 // rows' offsets and diagonal, then the gathers), products are staged in LDS
 // and each row is summed by a group of lanes sized to the tile.  Blocks are
-// remapped so each XCD works on one contiguous range of tiles.
+// remapped so each XCD works on chunks of consecutive tiles (xcd_remap).
 //
 // The same launch sequence serves one graph and a batch of graphs: in a batch
 // every tile names its graph, whose CSR, values, I/O and row offset in the
