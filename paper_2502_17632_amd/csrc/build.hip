@@ -130,7 +130,7 @@ struct NetArgs {
   int32_t *pin_net;  // net of every pin slot
   uint32_t *flag;
   uint32_t *tmp32;   // scratch of the global merge sort [P]
-  const int32_t *tiles;
+  const TileDesc *tiles;  // nets [r0, r1), pins [p0, p1) of every tile
 };
 
 // Writes the distinct values of the sorted keys src[0..n) to out[0..) and
@@ -205,8 +205,8 @@ static_assert(kNetSortCap * 4 <= kNetSmem && kChunk32 * 4 <= kNetSmem, "long net
 __global__ __launch_bounds__(kBlock) void k_net_tiles(NetArgs a) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[kNetSmem];
   __shared__ int bad_s;
-  const int64_t e0 = a.tiles[blockIdx.x], e1 = a.tiles[blockIdx.x + 1];
-  const int64_t q0 = a.net_ptr[e0], q1 = a.net_ptr[e1];
+  const TileDesc td = a.tiles[blockIdx.x];
+  const int64_t e0 = td.r0, e1 = td.r1, q0 = td.p0, q1 = td.p1;
   const int ns = static_cast<int>(e1 - e0);
   const int64_t n64 = q1 - q0;
   if (ns == 1 && n64 > kBLongRow) {
@@ -407,7 +407,7 @@ struct RowArgs {
   uint64_t *zkey;   // emitted keys (also scratch of the global merge sort)
   uint64_t *zsort;  // sorted keys
   int32_t *ucnt;    // distinct columns per row
-  const int32_t *tiles;
+  const TileDesc *tiles;  // rows [r0, r1), emitted keys [p0, p1) of every tile
   KeyLayout L;
 };
 
@@ -428,8 +428,8 @@ static_assert(kRowSortCap * 8 <= kSortSmem && kChunk64 * 8 <= kSortSmem, "long r
 __global__ __launch_bounds__(kBlock) void k_row_sort_tiles(RowArgs a) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[kSortSmem];
   __shared__ int32_t tmp[kBlock / kWave];
-  const int64_t r0 = a.tiles[blockIdx.x], r1 = a.tiles[blockIdx.x + 1];
-  const int64_t z0 = a.zoff[r0], z1 = a.zoff[r1];
+  const TileDesc td = a.tiles[blockIdx.x];
+  const int64_t r0 = td.r0, r1 = td.r1, z0 = td.p0, z1 = td.p1;
   const int ns = static_cast<int>(r1 - r0);
   const int64_t n64 = z1 - z0;
   if (ns == 1 && n64 > kBLongRow) {
@@ -510,7 +510,7 @@ struct MergeArgs {
   const uint64_t *zsort;
   const double *wnet;
   const int32_t *row_ptr;
-  const int32_t *tiles;
+  const TileDesc *tiles;  // as in the row sort
   int32_t *col;
   double *w;
   double *deg;
@@ -547,8 +547,8 @@ static_assert((kBTileCap + 1) * 16 + 2 * (kBTileRows + 2) * 4 + (kBTileCap + 1) 
 __global__ __launch_bounds__(kBlock) void k_row_merge_tiles(MergeArgs a) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[kMergeSmem];
   __shared__ int32_t tmp[kBlock / kWave];
-  const int64_t r0 = a.tiles[blockIdx.x], r1 = a.tiles[blockIdx.x + 1];
-  const int64_t z0 = a.zoff[r0], z1 = a.zoff[r1];
+  const TileDesc td = a.tiles[blockIdx.x];
+  const int64_t r0 = td.r0, r1 = td.r1, z0 = td.p0, z1 = td.p1;
   const int ns = static_cast<int>(r1 - r0);
   const int64_t n64 = z1 - z0;
   const int64_t o0 = a.row_ptr[r0];
@@ -865,9 +865,13 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
   GIFT_TRY(sc.get(&pin_net, P, "pin nets"));
   GIFT_TRY(sc.get(&tmp32, P, "net sort scratch"));
 
-  // 1. distinct cells per net
+  // 1. distinct cells per net (tile descriptors first: one load per block
+  //    instead of two dependent ones; pin offsets fit int32 by the check above)
+  TileDesc *net_descs = nullptr;
+  GIFT_TRY(sc.get(&net_descs, num_net_tiles + 1, "net tile descriptors"));
+  GIFT_TRY(tile_descs(net_tiles, net_ptr, num_net_tiles, st, net_descs));
   if (num_net_tiles > 0) {
-    NetArgs na{net_ptr, pin, E, P, N, M, ucell, pin_net, flag, tmp32, net_tiles};
+    NetArgs na{net_ptr, pin, E, P, N, M, ucell, pin_net, flag, tmp32, net_descs};
     k_net_tiles<<<static_cast<unsigned>(num_net_tiles), kBlock, 0, st>>>(na);
     GIFT_TRY(check_launch("k_net_tiles"));
   }
@@ -937,6 +941,11 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
   GIFT_TRY(dev_alloc(reinterpret_cast<void **>(&g->deg), R * 8, st, "degrees"));
   g->bytes = (R + 1) * 4 + cap * 12 + R * 8;
 
+  // row tile descriptors (key offsets fit int32: Z <= cap, checked above)
+  TileDesc *row_descs = nullptr;
+  GIFT_TRY(sc.get(&row_descs, num_row_tiles + 1, "row tile descriptors"));
+  GIFT_TRY(tile_descs(row_tiles, zoff, num_row_tiles, st, row_descs));
+
   // 3b. emit
   uint64_t *zkey = nullptr, *zsort = nullptr;
   int32_t *ucnt = nullptr;
@@ -948,7 +957,7 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
 
   // 4. sort rows
   if (num_row_tiles > 0) {
-    RowArgs ra{zoff, zkey, zsort, ucnt, row_tiles, L};
+    RowArgs ra{zoff, zkey, zsort, ucnt, row_descs, L};
     k_row_sort_tiles<<<static_cast<unsigned>(num_row_tiles), kBlock, 0, st>>>(ra);
     GIFT_TRY(check_launch("k_row_sort_tiles"));
   }
@@ -988,7 +997,7 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
   for (int c = 0; c < kTileClasses && ss == GIFT_OK; ++c)
     ss = build_tiles64(rp64, R, N, kSpmmTiles[c], side.stream, tstart[c], tile_counts + 2 * c);
   if (ss == GIFT_OK && num_row_tiles > 0) {
-    MergeArgs ma{zoff, zsort, wnet, g->row_ptr, row_tiles, g->col, g->w, g->deg,
+    MergeArgs ma{zoff, zsort, wnet, g->row_ptr, row_descs, g->col, g->w, g->deg,
                  L, N, d->weight_model};
     k_row_merge_tiles<<<static_cast<unsigned>(num_row_tiles), kBlock, 0, st>>>(ma);
     ss = check_launch("k_row_merge_tiles");
