@@ -55,6 +55,15 @@ constexpr int kNetSortCap = 2048;  // longest net sorted in LDS (32-bit keys, 8 
 constexpr int kRowSortCap = 2048;  // longest row sorted in LDS (64-bit keys, 16 KB)
 constexpr int kChunk32 = 2048;     // LDS chunk of the global merge sort (u32)
 constexpr int kChunk64 = 2048;     // LDS chunk of the global merge sort (u64)
+// Items per thread when a block stages a tile's offsets (up to kBTileRows + 1),
+// its entries (up to kBTileCap) or a long row (up to 2048) into LDS.  Each
+// thread issues all its loads before its first store, so a block waits for
+// one memory latency instead of one per item.
+constexpr int kOffItems = (kBTileRows + 1 + kBlock - 1) / kBlock;
+constexpr int kTileItems = (kBTileCap + kBlock - 1) / kBlock;
+constexpr int kLongItems = 2048 / kBlock;
+static_assert(kNetSortCap <= kLongItems * kBlock && kRowSortCap <= kLongItems * kBlock,
+              "long rows staged in one pass");
 
 __device__ __forceinline__ double clique_weight(int64_t m, int model) {
   return model == GIFT_W_TWO_OVER_M ? 2.0 / static_cast<double>(m)
@@ -163,15 +172,20 @@ __device__ __forceinline__ void net_long(const NetArgs &a, int64_t e, int64_t lo
   int64_t m;
   if (n <= kNetSortCap) {
     const int np = next_pow2_i(static_cast<int>(n));
-    for (int i = threadIdx.x; i < np; i += kBlock) {
-      uint32_t k = 0xffffffffu;
+    int32_t c[kLongItems];
+#pragma unroll
+    for (int k = 0; k < kLongItems; ++k) {
+      const int i = threadIdx.x + k * kBlock;
+      c[k] = i < n ? a.pin[lo + i] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < kLongItems; ++k) {
+      const int i = threadIdx.x + k * kBlock;
       if (i < n) {
-        const int32_t c = a.pin[lo + i];
         a.pin_net[lo + i] = static_cast<int32_t>(e);
-        if (c < 0 || c >= a.N) bad_s = 1;
-        k = static_cast<uint32_t>(c);
+        if (c[k] < 0 || c[k] >= a.N) bad_s = 1;
       }
-      keys[i] = k;
+      if (i < np) keys[i] = i < n ? static_cast<uint32_t>(c[k]) : 0xffffffffu;
     }
     __syncthreads();
     lds_bitonic_sort<uint32_t>(keys, np);
@@ -220,33 +234,62 @@ __global__ __launch_bounds__(kBlock) void k_net_tiles(NetArgs a) {
   uint8_t *first = reinterpret_cast<uint8_t *>(seg + kBTileCap + 1);
   if (threadIdx.x == 0) bad_s = 0;
   __syncthreads();
-  for (int k = threadIdx.x; k <= ns; k += kBlock) loff[k] = static_cast<int32_t>(a.net_ptr[e0 + k] - q0);
-  for (int i = threadIdx.x; i < n; i += kBlock) {
-    const int32_t c = a.pin[q0 + i];
-    if (c < 0 || c >= a.N) bad_s = 1;
-    key[i] = static_cast<uint32_t>(c);
+  {
+    int64_t o[kOffItems];
+    int32_t c[kTileItems];
+#pragma unroll
+    for (int k = 0; k < kOffItems; ++k) {
+      const int i = threadIdx.x + k * kBlock;
+      o[k] = i <= ns ? a.net_ptr[e0 + i] : q0;
+    }
+#pragma unroll
+    for (int k = 0; k < kTileItems; ++k) {
+      const int i = threadIdx.x + k * kBlock;
+      c[k] = i < n ? a.pin[q0 + i] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < kOffItems; ++k) {
+      const int i = threadIdx.x + k * kBlock;
+      if (i <= ns) loff[i] = static_cast<int32_t>(o[k] - q0);
+    }
+#pragma unroll
+    for (int k = 0; k < kTileItems; ++k) {
+      const int i = threadIdx.x + k * kBlock;
+      if (i < n) {
+        if (c[k] < 0 || c[k] >= a.N) bad_s = 1;
+        key[i] = static_cast<uint32_t>(c[k]);
+      }
+    }
   }
   __syncthreads();
   fill_segment_ids(loff, ns, seg);
   __syncthreads();
+  // (both loops take four pins per step, so four LDS reads are in flight
+  // per wait)
   for (int i = threadIdx.x; i < n; i += kBlock) {
     const int k = seg[i];
     a.pin_net[q0 + i] = static_cast<int32_t>(e0 + k);
-    uint8_t f = 1;
-    for (int j = loff[k]; j < i; ++j)
-      if (key[j] == key[i]) {
-        f = 0;
-        break;
-      }
-    first[i] = f;
+    const uint32_t me = key[i];
+    bool f = true;
+    int j = loff[k];
+    for (; j + 4 <= i; j += 4)
+      f = f & (key[j] != me) & (key[j + 1] != me) & (key[j + 2] != me) & (key[j + 3] != me);
+    for (; j < i; ++j) f = f & (key[j] != me);
+    first[i] = f ? 1 : 0;
   }
   __syncthreads();
   for (int i = threadIdx.x; i < n; i += kBlock) {
     if (!first[i]) continue;
     const int k = seg[i];
+    const uint32_t me = key[i];
     int ur = 0;
-    for (int j = loff[k]; j < loff[k + 1]; ++j) ur += (first[j] && key[j] < key[i]) ? 1 : 0;
-    a.ucell[q0 + loff[k] + ur] = static_cast<int32_t>(key[i]);
+    int j = loff[k];
+    const int end = loff[k + 1];
+    for (; j + 4 <= end; j += 4)
+      ur += ((first[j] != 0) & (key[j] < me)) + ((first[j + 1] != 0) & (key[j + 1] < me)) +
+            ((first[j + 2] != 0) & (key[j + 2] < me)) + ((first[j + 3] != 0) & (key[j + 3] < me));
+    for (; j < end; ++j) ur += (first[j] && key[j] < me) ? 1 : 0;
+    a.ucell[q0 + loff[k] + ur] = static_cast<int32_t>(me);
   }
   for (int k = threadIdx.x; k < ns; k += kBlock) {
     int m = 0;
@@ -437,7 +480,17 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_tiles(RowArgs a) {
     int32_t total;
     if (n64 <= kRowSortCap) {
       const int np = next_pow2_i(static_cast<int>(n64));
-      for (int i = threadIdx.x; i < np; i += kBlock) keys[i] = i < n64 ? a.zkey[z0 + i] : ~0ull;
+      uint64_t v[kLongItems];
+#pragma unroll
+      for (int k = 0; k < kLongItems; ++k) {
+        const int i = threadIdx.x + k * kBlock;
+        v[k] = i < n64 ? a.zkey[z0 + i] : ~0ull;
+      }
+#pragma unroll
+      for (int k = 0; k < kLongItems; ++k) {
+        const int i = threadIdx.x + k * kBlock;
+        if (i < np) keys[i] = v[k];
+      }
       __syncthreads();
       lds_bitonic_sort<uint64_t>(keys, np);
       for (int i = threadIdx.x; i < n64; i += kBlock) a.zsort[z0 + i] = keys[i];
@@ -458,28 +511,58 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_tiles(RowArgs a) {
   int32_t *loff = reinterpret_cast<int32_t *>(key + kBTileCap + 1);
   uint16_t *seg = reinterpret_cast<uint16_t *>(loff + kBTileRows + 2);
   uint8_t *head = reinterpret_cast<uint8_t *>(seg + kBTileCap + 1);
-  for (int k = threadIdx.x; k <= ns; k += kBlock) loff[k] = static_cast<int32_t>(a.zoff[r0 + k] - z0);
-  for (int i = threadIdx.x; i < n; i += kBlock) key[i] = a.zkey[z0 + i];
+  {
+    int64_t o[kOffItems];
+    uint64_t v[kTileItems];
+#pragma unroll
+    for (int k = 0; k < kOffItems; ++k) {
+      const int i = threadIdx.x + k * kBlock;
+      o[k] = i <= ns ? a.zoff[r0 + i] : z0;
+    }
+#pragma unroll
+    for (int k = 0; k < kTileItems; ++k) {
+      const int i = threadIdx.x + k * kBlock;
+      v[k] = i < n ? a.zkey[z0 + i] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < kOffItems; ++k) {
+      const int i = threadIdx.x + k * kBlock;
+      if (i <= ns) loff[i] = static_cast<int32_t>(o[k] - z0);
+    }
+#pragma unroll
+    for (int k = 0; k < kTileItems; ++k) {
+      const int i = threadIdx.x + k * kBlock;
+      if (i < n) key[i] = v[k];
+    }
+  }
   __syncthreads();
   fill_segment_ids(loff, ns, seg);
   __syncthreads();
   // rank of each key in its row (keys of a row are distinct); the key is the
   // first of its column when no smaller key of the row has the same column
+  // (four keys per step, so four LDS reads are in flight per wait)
   for (int i = threadIdx.x; i < n; i += kBlock) {
     const int k = seg[i];
     const uint64_t me = key[i];
-    const uint32_t mc = key_col(me, a.L);
+    // keys of the same column that sort before me lie in [first_of_col, me)
+    const uint64_t col_lo = (me >> a.L.col_shift) << a.L.col_shift;
     int rank = 0;
-    uint8_t h = 1;
-    for (int j = loff[k]; j < loff[k + 1]; ++j) {
+    bool h = true;
+    int j = loff[k];
+    const int end = loff[k + 1];
+    for (; j + 4 <= end; j += 4) {
+      const uint64_t o0 = key[j], o1 = key[j + 1], o2 = key[j + 2], o3 = key[j + 3];
+      rank += (o0 < me ? 1 : 0) + (o1 < me ? 1 : 0) + (o2 < me ? 1 : 0) + (o3 < me ? 1 : 0);
+      h = h & !(o0 >= col_lo & o0 < me) & !(o1 >= col_lo & o1 < me) &
+          !(o2 >= col_lo & o2 < me) & !(o3 >= col_lo & o3 < me);
+    }
+    for (; j < end; ++j) {
       const uint64_t o = key[j];
-      if (o < me) {
-        ++rank;
-        if (key_col(o, a.L) == mc) h = 0;
-      }
+      rank += o < me ? 1 : 0;
+      h = h & !(o >= col_lo & o < me);
     }
     a.zsort[z0 + loff[k] + rank] = me;
-    head[i] = h;
+    head[i] = h ? 1 : 0;
   }
   __syncthreads();
   for (int k = threadIdx.x; k < ns; k += kBlock) {
@@ -590,11 +673,35 @@ __global__ __launch_bounds__(kBlock) void k_row_merge_tiles(MergeArgs a) {
   int32_t *loff = reinterpret_cast<int32_t *>(mw + kBTileCap + 1);
   int32_t *moff = loff + kBTileRows + 2;
   uint16_t *seg = reinterpret_cast<uint16_t *>(moff + kBTileRows + 2);
-  for (int k = threadIdx.x; k <= ns; k += kBlock) {
-    loff[k] = static_cast<int32_t>(a.zoff[r0 + k] - z0);
-    moff[k] = static_cast<int32_t>(a.row_ptr[r0 + k] - o0);
+  {
+    int64_t o[kOffItems];
+    int32_t m[kOffItems];
+    uint64_t v[kTileItems];
+#pragma unroll
+    for (int k = 0; k < kOffItems; ++k) {
+      const int i = threadIdx.x + k * kBlock;
+      o[k] = i <= ns ? a.zoff[r0 + i] : z0;
+      m[k] = i <= ns ? a.row_ptr[r0 + i] : static_cast<int32_t>(o0);
+    }
+#pragma unroll
+    for (int k = 0; k < kTileItems; ++k) {
+      const int i = threadIdx.x + k * kBlock;
+      v[k] = i < n ? a.zsort[z0 + i] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < kOffItems; ++k) {
+      const int i = threadIdx.x + k * kBlock;
+      if (i <= ns) {
+        loff[i] = static_cast<int32_t>(o[k] - z0);
+        moff[i] = static_cast<int32_t>(m[k] - o0);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kTileItems; ++k) {
+      const int i = threadIdx.x + k * kBlock;
+      if (i < n) key[i] = v[k];
+    }
   }
-  for (int i = threadIdx.x; i < n; i += kBlock) key[i] = a.zsort[z0 + i];
   __syncthreads();
   fill_segment_ids(loff, ns, seg);
   __syncthreads();
