@@ -751,7 +751,20 @@ __global__ __launch_bounds__(kBlock) void k_star_rows(const int32_t *virt_net,
     const int32_t m = M[e];
     const double g = wnet[e];
     const int64_t out = row_ptr[N + v];
-    for (int32_t i = lane; i < m; i += kWave) {
+    int32_t i = lane;
+    for (; i + 3 * kWave < m; i += 4 * kWave) {  // four loads in flight per lane
+      const int32_t c0 = ucell[lo + i], c1 = ucell[lo + i + kWave];
+      const int32_t c2 = ucell[lo + i + 2 * kWave], c3 = ucell[lo + i + 3 * kWave];
+      col[out + i] = c0;
+      col[out + i + kWave] = c1;
+      col[out + i + 2 * kWave] = c2;
+      col[out + i + 3 * kWave] = c3;
+      w[out + i] = g;
+      w[out + i + kWave] = g;
+      w[out + i + 2 * kWave] = g;
+      w[out + i + 3 * kWave] = g;
+    }
+    for (; i < m; i += kWave) {
       col[out + i] = ucell[lo + i];
       w[out + i] = g;
     }
