@@ -20,11 +20,13 @@ def _netlist(num_cells, nets):
     return num_cells, net_ptr, pins
 
 
-def _check(gift, torch, n, net_ptr, pins, threshold, tol=1e-11, what=""):
-    g = gift.build_graph(n, net_ptr, pins, star_threshold=threshold, sigmas=[1.0])
+def _check(gift, torch, n, net_ptr, pins, threshold, tol=1e-11, what="", model="inv_m1"):
+    g = gift.build_graph(n, net_ptr, pins, star_threshold=threshold, sigmas=[1.0],
+                         weight_model=model)
     y, info, lab = gift.eigen_placement(g, tol=tol, max_iter=2000, labels=True)
     torch.cuda.synchronize()
-    lam, vec, labels, gl, full = EG.eigen_placement(n, net_ptr, pins)
+    lam, vec, labels, gl, full = EG.eigen_placement(n, net_ptr, pins,
+                                                    1 if model == "two_over_m" else 0)
     yh = y.cpu().numpy()
     log(f"[eigen] {what}: lambda {info['lambda']} (oracle {lam}), residual {info['residual']}, "
         f"{info['iterations']} iterations, {info['sweeps']} sweeps, component {gl} "
@@ -62,6 +64,16 @@ def test_star_nets_are_eliminated_exactly(threshold):
     nl = W.sized(1500, seed=7)
     _check(gift, torch, nl.num_cells, nl.net_ptr, nl.pin_cell, threshold,
            what=f"1.5k cells, star threshold {threshold}")
+
+
+def test_two_over_m_weights():
+    """The 2/M weight model (Section 2.2, eq. wire_eq): stars of weight
+    M w(M) = 2 still eliminate exactly."""
+    import torch
+    import paper_2502_17632_amd as gift
+    nl = W.sized(1200, seed=9)
+    _check(gift, torch, nl.num_cells, nl.net_ptr, nl.pin_cell, 16, what="2/M weights",
+           model="two_over_m")
 
 
 def test_giant_component_is_not_the_first():
