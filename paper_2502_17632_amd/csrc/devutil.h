@@ -72,11 +72,11 @@ __host__ __device__ constexpr int next_pow2_i(int v) {
 }
 
 // Sorts a[0..n) ascending with one block, using b[0..n) as scratch and `lds`
-// (kChunk keys of LDS) for the first round.  Returns true when the sorted
+// (kChunk keys of LDS) for the first pass.  Returns true when the sorted
 // keys end in b, false when they end in a.
 template <typename K, int kChunk>
 __device__ bool block_merge_sort_global(K *a, K *b, int64_t n, K *lds, K pad) {
-  // Round 1: sort chunks of kChunk keys in LDS, in place in a.
+  // First pass: sort chunks of kChunk keys in LDS, in place in a.
   for (int64_t c0 = 0; c0 < n; c0 += kChunk) {
     int len = static_cast<int>((n - c0) < kChunk ? (n - c0) : kChunk);
     int np = next_pow2_i(len);
@@ -86,7 +86,7 @@ __device__ bool block_merge_sort_global(K *a, K *b, int64_t n, K *lds, K pad) {
     for (int i = threadIdx.x; i < len; i += kBlock) a[c0 + i] = lds[i];
     __syncthreads();
   }
-  // Merge rounds: runs of width w -> 2w, ping-ponging between a and b.
+  // Merge passes: runs of width w -> 2w, ping-ponging between a and b.
   K *src = a, *dst = b;
   bool in_b = false;
   constexpr int kItems = 8;
