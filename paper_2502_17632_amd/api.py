@@ -52,6 +52,8 @@ class Graph:
     def __init__(self, handle: C.c_void_p, stream):
         self._h = handle
         self._stream = stream
+        # the device the graph was built on (its memory lives there)
+        self.device = torch.device("cuda", torch.cuda.current_device())
 
     @property
     def handle(self):
@@ -214,14 +216,15 @@ def eigen_placement(graph: Graph, *, tol: float = 1e-10, max_iter: int = 1000,
     tensor, info dict[, int32 labels of every graph row])."""
     inf = graph.info()
     n, r = inf["num_cells"], inf["num_rows"]
-    dev = torch.device("cuda", torch.cuda.current_device())
+    dev = graph.device
     out = torch.empty((n, 2), dtype=torch.float64, device=dev)
     lab = torch.empty(r, dtype=torch.int32, device=dev) if labels else None
     res = L.EigenResult()
-    L.check(L.lib().gift_eigen_placement(graph.handle, float(tol), int(max_iter),
-                                         int(seed) & 0xFFFFFFFFFFFFFFFF, _ptr(out), 2,
-                                         _ptr(lab), C.byref(res), _stream_handle(stream)),
-            "gift_eigen_placement")
+    with torch.cuda.device(dev):
+        L.check(L.lib().gift_eigen_placement(graph.handle, float(tol), int(max_iter),
+                                             int(seed) & 0xFFFFFFFFFFFFFFFF, _ptr(out), 2,
+                                             _ptr(lab), C.byref(res), _stream_handle(stream)),
+                "gift_eigen_placement")
     lam = getattr(res, "lambda")
     info = {"lambda": [lam[0], lam[1]],
             "residual": [res.residual[0], res.residual[1]],
