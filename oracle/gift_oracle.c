@@ -484,3 +484,52 @@ int oracle_bin_density(int64_t n, const double *x, const double *w, const double
   }
   return ORACLE_OK;
 }
+
+/* A caller-supplied weighted graph: the undirected weighted graph that
+ * Section 2.1 defines (A = {w_ij}, D = diag(sum_j w_ij)) and that Algorithm 1
+ * takes as its input.  The CSR must be canonical: row_ptr[0] = 0,
+ * non-decreasing, row_ptr[R] = nnz; columns strictly ascending within a row,
+ * in [0, R) and never equal to the row (the self-loop is sigma, added in
+ * eq. A_formulation); weights finite and >= 0.  Every row is a cell (no
+ * virtual rows).  Degrees as in O4: the row's weights summed left to right.
+ * Symmetry w_ij = w_ji is the caller's: the definitions above do not need it. */
+int oracle_import_csr(int64_t num_rows, int64_t nnz, const int64_t *row_ptr,
+                      const int32_t *col, const double *w, oracle_graph **out) {
+  *out = NULL;
+  if (num_rows < 0 || nnz < 0) return ORACLE_EINVAL;
+  if (row_ptr[0] != 0 || row_ptr[num_rows] != nnz) return ORACLE_EINVAL;
+  for (int64_t r = 0; r < num_rows; ++r) {
+    if (row_ptr[r + 1] < row_ptr[r]) return ORACLE_EINVAL;
+    for (int64_t p = row_ptr[r]; p < row_ptr[r + 1]; ++p) {
+      if (col[p] < 0 || col[p] >= num_rows || col[p] == r) return ORACLE_EINVAL;
+      if (p > row_ptr[r] && col[p] <= col[p - 1]) return ORACLE_EINVAL;
+      if (!(w[p] >= 0.0) || !isfinite(w[p])) return ORACLE_EINVAL;
+    }
+  }
+  oracle_graph *g = (oracle_graph *)calloc(1, sizeof(oracle_graph));
+  if (!g) return ORACLE_ENOMEM;
+  g->num_cells = num_rows;
+  g->num_rows = num_rows;
+  g->nnz = nnz;
+  g->row_ptr = (int64_t *)malloc(sizeof(int64_t) * (size_t)(num_rows + 1));
+  g->col = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+  g->w = (double *)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+  g->deg = (double *)malloc(sizeof(double) * (size_t)(num_rows > 0 ? num_rows : 1));
+  g->ucell_ptr = (int64_t *)calloc(1, sizeof(int64_t));
+  if (!g->row_ptr || !g->col || !g->w || !g->deg || !g->ucell_ptr) {
+    oracle_free(g);
+    return ORACLE_ENOMEM;
+  }
+  memcpy(g->row_ptr, row_ptr, sizeof(int64_t) * (size_t)(num_rows + 1));
+  if (nnz > 0) {
+    memcpy(g->col, col, sizeof(int32_t) * (size_t)nnz);
+    memcpy(g->w, w, sizeof(double) * (size_t)nnz);
+  }
+  for (int64_t r = 0; r < num_rows; ++r) {
+    double d = 0.0;
+    for (int64_t p = g->row_ptr[r]; p < g->row_ptr[r + 1]; ++p) d = d + g->w[p];
+    g->deg[r] = d;
+  }
+  *out = g;
+  return ORACLE_OK;
+}

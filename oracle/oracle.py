@@ -47,6 +47,8 @@ def load(path: Optional[str] = None):
     lib.oracle_bin_density.argtypes = [i64, vp, vp, vp, C.c_double, C.c_double, C.c_double,
                                        C.c_double, i64, i64, vp]
     lib.oracle_bin_density.restype = C.c_int
+    lib.oracle_import_csr.argtypes = [i64, i64, vp, vp, vp, C.POINTER(vp)]
+    lib.oracle_import_csr.restype = C.c_int
     if path is None:
         _lib = lib
     return lib
@@ -180,6 +182,28 @@ def build_graph(num_cells: int, net_ptr: np.ndarray, pin_cell: np.ndarray, *,
     vn = np.empty(v, dtype=np.int32)
     lib.oracle_export(h, _ptr(row_ptr), _ptr(col), _ptr(w), _ptr(deg), _ptr(vn))
     return OracleGraph(n, v, row_ptr, col, w, deg, vn, h, lib)
+
+
+def import_csr(row_ptr: np.ndarray, col: np.ndarray, w: np.ndarray, lib=None) -> OracleGraph:
+    """A caller-supplied weighted graph in canonical CSR (see
+    oracle_import_csr): every row is a cell, degrees are summed in ascending
+    column."""
+    lib = lib or load()
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    r = row_ptr.shape[0] - 1
+    nnz = col.shape[0]
+    if w.shape[0] != nnz or r < 0:
+        raise OracleError("row_ptr / col / w sizes disagree")
+    h = C.c_void_p()
+    rc = lib.oracle_import_csr(r, nnz, _ptr(row_ptr), _ptr(col), _ptr(w), C.byref(h))
+    if rc:
+        raise OracleError(f"oracle_import_csr failed ({rc})")
+    deg = np.empty(r, dtype=np.float64)
+    lib.oracle_export(h, None, None, None, _ptr(deg), None)
+    return OracleGraph(r, 0, row_ptr.copy(), col.copy(), w.copy(), deg,
+                       np.empty(0, dtype=np.int32), h, lib)
 
 
 def build_netlist(netlist, **kw) -> OracleGraph:

@@ -505,11 +505,96 @@ def pin_eigen_components(lib, eig=None):
             assert np.all(lab[members] == members.min())
 
 
+def _csr_of_dense(a):
+    """Canonical CSR (ascending columns, no diagonal) of a dense matrix."""
+    rows, cols = np.nonzero(a)
+    keep = rows != cols
+    rows, cols = rows[keep], cols[keep]
+    row_ptr = np.zeros(a.shape[0] + 1, dtype=np.int64)
+    np.add.at(row_ptr, rows + 1, 1)
+    return np.cumsum(row_ptr), cols.astype(np.int32), a[rows, cols].astype(np.float64)
+
+
+def pin_import_csr(lib):
+    """A caller-supplied weighted graph (Section 2.1's A = {w_ij}, the input of
+    Algorithm 1): the paper's two-cell example through the import path; the
+    weighted complete graph's closed form; degrees bit-equal to a dense
+    left-to-right sum and the filter equal to the dense spectral form on
+    random weighted graphs; the CSR a netlist builds, imported, gives the same
+    bits; malformed CSRs are refused."""
+    gd = _read_golden("two_cell_paper_filter.txt")
+    g = O.import_csr(np.array([0, 1, 2]), np.array([1, 0]), np.array([1.0, 1.0]), lib=lib)
+    y = g.filter(np.array([float(v) for v in gd["x"]])[:, None],
+                 [float(v) for v in gd["sigma"]], [int(v) for v in gd["order"]],
+                 [float(v) for v in gd["alpha"]])
+    assert np.allclose(y[:, 0], [float(v) for v in gd["expected"]], rtol=0, atol=1e-15)
+    g.close()
+    # complete graph K_M with one weight w: A~^k x = xbar 1 + mu^k (x - xbar 1),
+    # mu = (sigma - w) / ((M - 1) w + sigma)
+    rng = np.random.default_rng(21)
+    for m, w in ((3, 0.37), (7, 2.5), (12, 0.125)):
+        a = w * (np.ones((m, m)) - np.eye(m))
+        rp, cl, wv = _csr_of_dense(a)
+        g = O.import_csr(rp, cl, wv, lib=lib)
+        assert np.allclose(g.deg, (m - 1) * w, rtol=1e-15, atol=0)
+        x = rng.normal(size=(m, 2)) * 10 + 300
+        xb = x.mean(axis=0, keepdims=True)
+        for s in (0.5, 4.0):
+            mu = (s - w) / ((m - 1) * w + s)
+            for k in (1, 3):
+                yk = g.filter(x, [s], [k], [1.0])
+                assert np.allclose(yk, xb + mu ** k * (x - xb), rtol=1e-13, atol=1e-12)
+        g.close()
+    # random symmetric weighted graphs with isolated nodes
+    cases = [([4.0] * 4, [1, 2, 4, 8], [0.25] * 4), ([0.0, 1.5], [2, 5], [0.4, 0.6])]
+    for trial in range(12):
+        n = int(rng.integers(2, 25))
+        a = np.triu(rng.random((n, n)) * (rng.random((n, n)) < 0.3) * rng.choice([0.25, 3.0, 1.0]), 1)
+        a = a + a.T
+        rp, cl, wv = _csr_of_dense(a)
+        g = O.import_csr(rp, cl, wv, lib=lib)
+        dd = D.dense_degree(a)
+        assert np.array_equal(g.deg.view(np.uint64), dd.view(np.uint64))
+        x = rng.normal(size=(n, 2)) * 30 + 500
+        for sig, k, al in cases:
+            ref = D.spectral_filter(a, x, sig, k, al)
+            err = np.abs(g.filter(x, sig, k, al) - ref).max() / np.abs(ref).max()
+            assert err <= 1e-12, (trial, err)
+        g.close()
+    # the CSR of a built netlist, imported, is the same graph bit for bit
+    net_ptr, pin_cell = _random_netlist(rng, 40, 60, 6)
+    gb = O.build_graph(40, net_ptr, pin_cell, lib=lib)
+    gi = O.import_csr(gb.row_ptr, gb.col, gb.w, lib=lib)
+    assert np.array_equal(gi.deg.view(np.uint64), gb.deg.view(np.uint64))
+    for s in (0.0, 2.0):
+        for u, v in zip(gb.normalise(s), gi.normalise(s)):
+            assert np.array_equal(u.view(np.uint64), v.view(np.uint64))
+    x = rng.normal(size=(40, 2)) * 20 + 500
+    assert np.array_equal(gb.filter(x, [4.0, 2.0], [3, 2], [0.5, 0.5]),
+                          gi.filter(x, [4.0, 2.0], [3, 2], [0.5, 0.5]))
+    gb.close()
+    gi.close()
+    bad = [([0, 1, 2], [1, 1], [1.0, 1.0]),          # row 1 holds its own diagonal
+           ([0, 2, 2], [1, 1], [1.0, 1.0]),          # repeated column
+           ([0, 2, 2], [1, 0], [1.0, 1.0]),          # diagonal, descending
+           ([0, 1, 2], [2, 0], [1.0, 1.0]),          # column out of range
+           ([0, 1, 2], [1, 0], [-1.0, 1.0]),         # negative weight
+           ([0, 1, 2], [1, 0], [np.nan, 1.0]),       # NaN weight
+           ([1, 1, 2], [1, 0], [1.0, 1.0]),          # row_ptr[0] != 0
+           ([0, 2, 1], [1, 0], [1.0, 1.0])]          # decreasing row_ptr
+    for rp, cl, wv in bad:
+        try:
+            O.import_csr(np.array(rp), np.array(cl), np.array(wv), lib=lib)
+        except O.OracleError:
+            continue
+        raise AssertionError(f"malformed CSR accepted: {rp} {cl} {wv}")
+
+
 ALL_PINS = [pin_golden_two_cell, pin_clique_closed_form, pin_hand_built,
             pin_brute_force_structure, pin_spectral, pin_theorem1_fixed_point,
             pin_spectrum, pin_isolated_and_fixed, pin_star_schur,
             pin_generated_invariants, pin_invalid_input, pin_evaluate_hand,
-            pin_evaluate_dense, pin_exact_filter, pin_bin_density]
+            pin_evaluate_dense, pin_exact_filter, pin_bin_density, pin_import_csr]
 
 # the eigenvector-placement oracle is numpy (oracle/eigen.py); its pins take
 # the module to check, so mutants of it can be run through them

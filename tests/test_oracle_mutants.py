@@ -31,6 +31,9 @@ MUTANTS = {
     "hpwl_min_not_tracked": ("if (ga < mn) mn = ga;", "if (ga < mn) mx = ga;"),
     "exact_filter_without_identity": ("q[i] = 2.0 * p[i] - acc;", "q[i] = p[i] - acc;"),
     "cg_beta_inverted": ("double beta = rho_new / rho;", "double beta = rho / rho_new;"),
+    "import_degree_skips_first": ("  for (int64_t r = 0; r < num_rows; ++r) {\n    double d = 0.0;\n    for (int64_t p = g->row_ptr[r]; p",
+                                  "  for (int64_t r = 0; r < num_rows; ++r) {\n    double d = 0.0;\n    for (int64_t p = g->row_ptr[r] + 1; p"),
+    "import_accepts_diagonal": ("col[p] >= num_rows || col[p] == r)", "col[p] >= num_rows)"),
     "density_overlap_not_clipped": ("double lx = (x1 < a1 ? x1 : a1) - (x0 > a0 ? x0 : a0);",
                                     "double lx = x1 - (x0 > a0 ? x0 : a0);"),
 }
