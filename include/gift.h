@@ -160,6 +160,59 @@ typedef struct {
 gift_status gift_build_graph(const gift_graph_desc *desc, void *stream, gift_graph **out);
 
 /*
+ * A caller-supplied weighted graph for gift_graph_import_csr: the undirected
+ * weighted graph that Section 2.1 defines (A = {w_ij}, D = diag(sum_j w_ij))
+ * and that Algorithm 1 takes as its input, as a canonical CSR.
+ *
+ *   num_rows   R >= 0 nodes.  Every node is a cell: row i of A is row i of
+ *              every signal (there are no star rows).
+ *   nnz        stored entries (off-diagonal weights), < 2^31 - 1.
+ *   row_ptr    int64[R+1]: row_ptr[0] = 0, non-decreasing, row_ptr[R] = nnz.
+ *   col        int32[nnz]: the columns of row i are col[row_ptr[i] ..
+ *              row_ptr[i+1]), strictly ascending, in [0, R) and never i (the
+ *              self-loop is sigma, added by eq. A_formulation).
+ *   w          double[nnz]: w_ij, finite and >= 0.
+ *   mem_space  where the three arrays live (GIFT_MEM_HOST or
+ *              GIFT_MEM_DEVICE); they are read during the call only.
+ *   storage, num_sigmas, sigmas   as in gift_graph_desc.
+ *
+ * The graph is used as given: symmetry w_ij = w_ji is the caller's (the
+ * method assumes an undirected graph; the definitions below do not need it).
+ */
+typedef struct {
+  int64_t num_rows;
+  int64_t nnz;
+  const int64_t *row_ptr;
+  const int32_t *col;
+  const double *w;
+  int32_t mem_space;
+  int32_t storage;
+  int32_t num_sigmas;
+  int32_t reserved; /* must be 0 */
+  const double *sigmas;
+} gift_csr_desc;
+
+/*
+ * gift_graph_import_csr -- caller-supplied weighted graph -> resident graph
+ * (Section 2.1; Algorithm 1, input; normalisation, eq. A_formulation).
+ *
+ * The result is what gift_build_graph produces from a netlist: the CSR of A
+ * (copied), float64 degrees d_i = sum_j w_ij summed in ascending column, the
+ * SpMM row tiles, and for every sigma the normalised values
+ * a_ij = (w_ij s_i) s_j and diagonal (sigma s_i) s_i with s_i = 1/sqrt(d_i +
+ * sigma) (0 when d_i + sigma = 0), rounded once to the storage type.  Every
+ * other entry point takes the graph like a built one (gift_evaluate_placement
+ * reports hpwl only when given a netlist).  The CSR is checked on the device;
+ * the call synchronises `stream` to read the result of the check and returns
+ * with the normalisation still enqueued on `stream`, as gift_build_graph does.
+ * Errors: GIFT_EINVAL (NULL pointers, negative sizes, a malformed CSR as
+ * described above, bad enums or sigmas), GIFT_EUNSUPPORTED (2^31 - 1 rows or
+ * entries or more), GIFT_ENOMEM, GIFT_EDEVICE.  On error *out is NULL and
+ * nothing is leaked.
+ */
+gift_status gift_graph_import_csr(const gift_csr_desc *desc, void *stream, gift_graph **out);
+
+/*
  * gift_filter_placement -- g' = sum_t alpha_t A~_{sigma_t}^{k_t} g
  * (eq. proposed_filter; Section 3.2.2 for the role of the result).
  *

@@ -9,6 +9,6 @@ does.
 """
 from .api import (Batch, Graph, Server, bin_density, build_graph,  # noqa: F401
                   density_overflow, eigen_placement, evaluate_placement,
-                  filter_exact, filter_placement, make_terms, profile_collect,
+                  filter_exact, filter_placement, import_csr, make_terms, profile_collect,
                   profile_enable)
 from ._lib import GiftError, lib  # noqa: F401

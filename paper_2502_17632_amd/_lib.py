@@ -33,6 +33,21 @@ class GraphDesc(C.Structure):
     ]
 
 
+class CsrDesc(C.Structure):
+    _fields_ = [
+        ("num_rows", C.c_int64),
+        ("nnz", C.c_int64),
+        ("row_ptr", C.c_void_p),
+        ("col", C.c_void_p),
+        ("w", C.c_void_p),
+        ("mem_space", C.c_int32),
+        ("storage", C.c_int32),
+        ("num_sigmas", C.c_int32),
+        ("reserved", C.c_int32),
+        ("sigmas", C.c_void_p),
+    ]
+
+
 class Term(C.Structure):
     _fields_ = [("sigma", C.c_double), ("order", C.c_int32), ("reserved", C.c_int32),
                 ("alpha", C.c_double)]
@@ -148,6 +163,7 @@ _lib = None
 # name -> (restype, argtypes)
 SIGNATURES = {
     "gift_build_graph": (C.c_int, [C.POINTER(GraphDesc), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "gift_graph_import_csr": (C.c_int, [C.POINTER(CsrDesc), C.c_void_p, C.POINTER(C.c_void_p)]),
     "gift_filter_placement": (C.c_int, [C.c_void_p, C.POINTER(Term), C.c_int32, C.c_void_p,
                                         C.c_int32, C.c_int64, C.c_int32, C.c_void_p, C.c_int64,
                                         C.c_int32, C.c_void_p, C.c_void_p]),

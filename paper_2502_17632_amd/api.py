@@ -149,6 +149,45 @@ def build_graph(num_cells: int, net_ptr, pin_cell, *, weight_model: str = "inv_m
     return Graph(h, stream)
 
 
+def import_csr(row_ptr, col, w, *, storage: str = "f32", sigmas: Iterable[float] = (4.0,),
+               stream=None) -> Graph:
+    """A caller-supplied weighted graph (canonical CSR of A: int64 row_ptr,
+    int32 col strictly ascending per row, float64 weights) -> resident graph.
+    The arrays may be numpy arrays (host) or CUDA tensors (device)."""
+    arrs = (row_ptr, col, w)
+    on_dev = [isinstance(a, torch.Tensor) for a in arrs]
+    if any(on_dev) and not all(on_dev):
+        raise TypeError("row_ptr, col and w must all be numpy arrays or all tensors")
+    if all(on_dev):
+        if not all(a.is_cuda for a in arrs):
+            raise TypeError("tensors must live on the GPU")
+        if (row_ptr.dtype, col.dtype, w.dtype) != (torch.int64, torch.int32, torch.float64):
+            raise TypeError("row_ptr must be int64, col int32 and w float64")
+        row_ptr, col, w = row_ptr.contiguous(), col.contiguous(), w.contiguous()
+        mem = L.GIFT_MEM_DEVICE
+    else:
+        row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        mem = L.GIFT_MEM_HOST
+    if row_ptr.shape[0] < 1 or col.shape[0] != w.shape[0]:
+        raise ValueError("row_ptr needs R + 1 >= 1 entries and col / w the same length")
+    sig = np.ascontiguousarray(list(sigmas), dtype=np.float64)
+    d = L.CsrDesc()
+    d.num_rows = int(row_ptr.shape[0]) - 1
+    d.nnz = int(col.shape[0])
+    d.row_ptr, d.col, d.w = _ptr(row_ptr), _ptr(col), _ptr(w)
+    d.mem_space = mem
+    d.storage = DTYPES[storage]
+    d.num_sigmas = int(sig.shape[0])
+    d.reserved = 0
+    d.sigmas = _ptr(sig)
+    h = C.c_void_p()
+    L.check(L.lib().gift_graph_import_csr(C.byref(d), _stream_handle(stream), C.byref(h)),
+            "gift_graph_import_csr")
+    return Graph(h, stream)
+
+
 def filter_placement(graph: Graph, sigma: Sequence[float], order: Sequence[int],
                      alpha: Sequence[float], x: torch.Tensor, *,
                      fixed: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,

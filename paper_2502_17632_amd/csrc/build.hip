@@ -894,7 +894,7 @@ gift_status prepare_sigma(gift_graph *g, double sigma, hipStream_t st) {
 
 namespace {
 
-constexpr int kMaxReadback = 8;
+constexpr int kMaxReadback = kReadScalarsMax;
 static_assert(kMaxReadback <= kReadbackSlots, "readback slots");
 
 // Copies int64 scalars from device memory into one small block so the host
@@ -905,6 +905,8 @@ struct ReadbackPtrs {
 __global__ void k_gather_i64(ReadbackPtrs src, int n, int64_t *dst) {
   if (threadIdx.x < n) dst[threadIdx.x] = *src.p[threadIdx.x];
 }
+
+}  // namespace
 
 // Reads `n` device int64 scalars with one launch and one wait: the kernel
 // writes them straight into a pinned host slot.  A slot whose wait failed is
@@ -926,6 +928,8 @@ gift_status read_scalars(hipStream_t st, const int64_t *const *ptrs, int n, int6
   readback_release(rb);
   return GIFT_OK;
 }
+
+namespace {
 
 gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) {
   const int64_t N = d->num_cells, E = d->num_nets;

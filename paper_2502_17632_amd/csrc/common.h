@@ -99,6 +99,11 @@ void readback_release(const Readback &r);
 // usual case: the readback ends a short chain of kernels), then blocks.
 gift_status readback_wait(const Readback &r, hipStream_t st);
 
+// Reads `n` (<= kReadScalarsMax) device int64 scalars with one launch and
+// one wait on `st`: a kernel writes them straight into a pinned host slot.
+constexpr int kReadScalarsMax = 8;
+gift_status read_scalars(hipStream_t st, const int64_t *const *ptrs, int n, int64_t *out);
+
 // A second stream (default priority) with two events, for work a call runs
 // beside its caller's stream: `ready` is recorded on the caller's stream and
 // waited on by `stream`; `done` is free for the caller.  From a per-device

@@ -115,10 +115,25 @@ def run_pair(netlist, x: np.ndarray, terms, *, storage: str = "f32", star_thresh
     return y, ref, g, og
 
 
+def spread_error(y: np.ndarray, ref: np.ndarray) -> np.ndarray:
+    """||y - y*||_inf / ||y* - mean(y*)||_inf per column: the error against
+    the spread of the placement rather than its distance from the origin."""
+    den = np.abs(ref - ref.mean(axis=0, keepdims=True)).max(axis=0)
+    den = np.where(den > 0, den, 1.0)
+    return np.abs(y - ref).max(axis=0) / den
+
+
+def rms_error(y: np.ndarray, ref: np.ndarray) -> np.ndarray:
+    """Root mean square of y - y* per column (absolute)."""
+    return np.sqrt(np.mean((y - ref) ** 2, axis=0))
+
+
 def assert_close(y, ref, storage: str, label: str = ""):
     err = colwise_error(y, ref)
     log(f"[parity] {label} normwise error per column: "
-        f"{' '.join(f'{e:.3e}' for e in err)} (tol {TOL[storage]:.1e})")
+        f"{' '.join(f'{e:.3e}' for e in err)} (tol {TOL[storage]:.1e}); spread-relative "
+        f"{' '.join(f'{e:.3e}' for e in spread_error(y, ref))}; rms "
+        f"{' '.join(f'{e:.3e}' for e in rms_error(y, ref))}")
     assert np.all(np.isfinite(y))
     assert np.all(err <= TOL[storage]), (label, err)
     return err

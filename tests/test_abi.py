@@ -43,7 +43,7 @@ def test_abi_version_and_status_strings():
     assert b"unknown" in lib.gift_status_string(99)
 
 
-STRUCTS = {"gift_graph_desc": L.GraphDesc, "gift_term": L.Term, "gift_graph_info": L.GraphInfo,
+STRUCTS = {"gift_graph_desc": L.GraphDesc, "gift_csr_desc": L.CsrDesc, "gift_term": L.Term, "gift_graph_info": L.GraphInfo,
            "gift_batch_io": L.BatchIO, "gift_batch_info": L.BatchInfo,
            "gift_server_config": L.ServerConfig, "gift_request": L.Request,
            "gift_request_result": L.RequestResult, "gift_server_stats": L.ServerStats,
@@ -204,3 +204,38 @@ def test_eigen_arguments_rejected_without_device_work():
     assert lib.gift_eigen_placement(None, 1e-8, 10, 1, y, 2, None, C.byref(res),
                                     None) == L.GIFT_EINVAL
     assert lib.gift_eigen_placement(None, 1e-8, 10, 1, y, 2, None, None, None) == L.GIFT_EINVAL
+
+
+@pytest.mark.parametrize("field,value", [("num_rows", -1), ("nnz", -3), ("storage", 9),
+                                         ("num_sigmas", 0), ("mem_space", 5), ("reserved", 1),
+                                         ("num_rows", 1 << 31)])
+def test_bad_csr_descriptor_fields(field, value):
+    import numpy as np
+    lib = L.lib()
+    rp = np.array([0, 1, 2], dtype=np.int64)
+    col = np.array([1, 0], dtype=np.int32)
+    w = np.array([1.0, 1.0])
+    sig = np.array([4.0])
+    d = L.CsrDesc(num_rows=2, nnz=2, row_ptr=rp.ctypes.data, col=col.ctypes.data,
+                  w=w.ctypes.data, mem_space=L.GIFT_MEM_HOST, storage=0, num_sigmas=1,
+                  reserved=0, sigmas=sig.ctypes.data)
+    setattr(d, field, value)
+    out = C.c_void_p()
+    st = lib.gift_graph_import_csr(C.byref(d), None, C.byref(out))
+    assert st in (L.GIFT_EINVAL, L.GIFT_EUNSUPPORTED) and out.value is None
+
+
+def test_host_csr_row_ptr_checked_before_device_work():
+    import numpy as np
+    lib = L.lib()
+    col = np.array([1, 0], dtype=np.int32)
+    w = np.array([1.0, 1.0])
+    sig = np.array([4.0])
+    for rp in ([1, 1, 2], [0, 1, 3]):
+        rp = np.array(rp, dtype=np.int64)
+        d = L.CsrDesc(num_rows=2, nnz=2, row_ptr=rp.ctypes.data, col=col.ctypes.data,
+                      w=w.ctypes.data, mem_space=L.GIFT_MEM_HOST, storage=0, num_sigmas=1,
+                      reserved=0, sigmas=sig.ctypes.data)
+        out = C.c_void_p()
+        assert lib.gift_graph_import_csr(C.byref(d), None, C.byref(out)) == L.GIFT_EINVAL
+    assert lib.gift_graph_import_csr(None, None, C.byref(out)) == L.GIFT_EINVAL
