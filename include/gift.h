@@ -240,6 +240,30 @@ gift_status gift_filter_placement(const gift_graph *graph, const gift_term *term
                                   const uint8_t *fixed_mask, void *stream);
 
 /*
+ * gift_filter_placement_noalloc -- gift_filter_placement for callers that
+ * cannot allocate device memory: code being captured into a HIP graph, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same arguments, the same
+ * kernels and so bit-identical results; it calls no hipMalloc, hipFree or
+ * other allocating routine.  Its signal buffers (x0, two ping-pong iterates
+ * and one saved iterate per distinct stored term, each R x the widest column
+ * chunk of 16, 8, 4, 2 or 1 columns in the storage type, rounded to 256
+ * bytes) live in a static 128 MiB device array that each GPU the library runs
+ * on holds until the process ends; inputs needing more fail with
+ * GIFT_EUNSUPPORTED and a message giving the size.  (F32, 2 columns and the
+ * five orders 1, 2, 4, 8, 16: 7 buffers of 8 bytes per row, up to about 2.3M
+ * rows.)  Every call on a GPU shares that GPU's array, so calls that overlap
+ * on one GPU (different streams or host threads without ordering) race and
+ * must be serialised by the caller; nothing in the array needs to start at
+ * zero.  Not timed by the library's profiler.  Errors as in
+ * gift_filter_placement, plus GIFT_EUNSUPPORTED for the size limit.
+ */
+gift_status gift_filter_placement_noalloc(const gift_graph *graph, const gift_term *terms,
+                                          int32_t num_terms, const void *x_in,
+                                          int32_t num_cols, int64_t ld_in, int32_t in_dtype,
+                                          void *y_out, int64_t ld_out, int32_t out_dtype,
+                                          const uint8_t *fixed_mask, void *stream);
+
+/*
  * gift_filter_exact -- the exact filter the paper's filter approximates
  * (Section 3.2.2: eq. incremental, eq. derivative, eq. spectral):
  *

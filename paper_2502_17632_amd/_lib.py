@@ -167,6 +167,10 @@ SIGNATURES = {
     "gift_filter_placement": (C.c_int, [C.c_void_p, C.POINTER(Term), C.c_int32, C.c_void_p,
                                         C.c_int32, C.c_int64, C.c_int32, C.c_void_p, C.c_int64,
                                         C.c_int32, C.c_void_p, C.c_void_p]),
+    "gift_filter_placement_noalloc": (C.c_int, [C.c_void_p, C.POINTER(Term), C.c_int32,
+                                                C.c_void_p, C.c_int32, C.c_int64, C.c_int32,
+                                                C.c_void_p, C.c_int64, C.c_int32, C.c_void_p,
+                                                C.c_void_p]),
     "gift_graph_add_sigma": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p]),
     "gift_filter_exact": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_int32, C.c_int64,
                                     C.c_int32, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p,

@@ -191,8 +191,11 @@ def import_csr(row_ptr, col, w, *, storage: str = "f32", sigmas: Iterable[float]
 def filter_placement(graph: Graph, sigma: Sequence[float], order: Sequence[int],
                      alpha: Sequence[float], x: torch.Tensor, *,
                      fixed: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
-                     out_dtype: torch.dtype = torch.float32, stream=None) -> torch.Tensor:
-    """g' = sum_t alpha_t A~_{sigma_t}^{order_t} x  (x: N x c CUDA tensor, f32/f64)."""
+                     out_dtype: torch.dtype = torch.float32, stream=None,
+                     no_alloc: bool = False) -> torch.Tensor:
+    """g' = sum_t alpha_t A~_{sigma_t}^{order_t} x  (x: N x c CUDA tensor, f32/f64).
+    ``no_alloc`` calls the variant whose signal buffers live in the library's
+    static scratch (no device allocation; calls on one GPU must not overlap)."""
     if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dim() == 2):
         raise TypeError("x must be a 2-D CUDA tensor")
     if x.stride(1) != 1:
@@ -211,11 +214,11 @@ def filter_placement(graph: Graph, sigma: Sequence[float], order: Sequence[int],
             raise TypeError("fixed must be a uint8 CUDA tensor with one entry per cell")
         fixed = fixed.contiguous()
     terms = make_terms(sigma, order, alpha)
-    L.check(L.lib().gift_filter_placement(graph.handle, terms, len(terms), _ptr(x), c,
-                                          x.stride(0), TORCH_DTYPES[x.dtype], _ptr(out),
-                                          out.stride(0), TORCH_DTYPES[out.dtype], _ptr(fixed),
-                                          _stream_handle(stream)),
-            "gift_filter_placement")
+    name = "gift_filter_placement_noalloc" if no_alloc else "gift_filter_placement"
+    L.check(getattr(L.lib(), name)(graph.handle, terms, len(terms), _ptr(x), c, x.stride(0),
+                                   TORCH_DTYPES[x.dtype], _ptr(out), out.stride(0),
+                                   TORCH_DTYPES[out.dtype], _ptr(fixed), _stream_handle(stream)),
+            name)
     return out
 
 

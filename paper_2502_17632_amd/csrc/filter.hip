@@ -21,6 +21,7 @@
 // shared signal buffers come from a small device table.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "common.h"
 #include "devutil.h"
@@ -809,12 +810,48 @@ gift_status exact_chunk_c(const gift_graph *g, const FilterPlan &pl, int C, doub
 
 using namespace gift;
 
-extern "C" gift_status gift_filter_placement(const gift_graph *g, const gift_term *terms,
-                                             int32_t nt, const void *x_in, int32_t num_cols,
-                                             int64_t ld_in, int32_t in_dt, void *y_out,
-                                             int64_t ld_out, int32_t out_dt,
-                                             const uint8_t *fixed, void *stream) {
-  clear_error();
+namespace gift {
+namespace {
+
+// The allocation-free variant's scratch: the chunk signal buffers (x0, ping,
+// pong and the saved iterates) live in this file-scope array instead of the
+// caching allocator.  Every GPU the library runs on holds its own copy until
+// the process ends; host code reaches it only through the address
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t kNoAllocScratchBytes = size_t(128) << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current).
+gift_status scratch_address(void **out) {
+  int dev = 0;
+  GIFT_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices)
+    return set_error(GIFT_EUNSUPPORTED, "device %d beyond the %d the scratch table holds", dev,
+                     kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    GIFT_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return set_error(GIFT_EDEVICE, "hipGetSymbolAddress returned NULL for the scratch");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return GIFT_OK;
+}
+
+// Shared by gift_filter_placement and its allocation-free variant.  With
+// `fixed_buf` NULL the chunk buffers come from the caching allocator;
+// otherwise they are carved from fixed_buf (cap bytes) and nothing is
+// allocated.
+gift_status filter_impl(const gift_graph *g, const gift_term *terms, int32_t nt, const void *x_in,
+                        int32_t num_cols, int64_t ld_in, int32_t in_dt, void *y_out,
+                        int64_t ld_out, int32_t out_dt, const uint8_t *fixed, void *stream,
+                        unsigned char *fixed_buf, size_t cap) {
   if (!g || !terms) return set_error(GIFT_EINVAL, "gift_filter_placement: NULL graph or terms");
   if (nt < 1 || nt > kMaxTerms) return set_error(GIFT_EINVAL, "num_terms %d not in [1, 64]", nt);
   if (num_cols < 1) return set_error(GIFT_EINVAL, "num_cols %d < 1", num_cols);
@@ -846,17 +883,53 @@ extern "C" gift_status gift_filter_placement(const gift_graph *g, const gift_ter
   pl.out_dtype = out_dt;
   pl.one = GraphDev{g->row_ptr, g->col, nullptr, nullptr, 0,
                     GraphIO{x_in, ld_in, y_out, ld_out, fixed, g->num_cells}};
+  if (fixed_buf) {
+    // the profiler creates events on first use; this path creates nothing
+    pl.profile = false;
+    const size_t need = chunk_buffer_bytes(pl, chunk_width(num_cols));
+    if (need > cap)
+      return set_error(GIFT_EUNSUPPORTED,
+                       "the allocation-free filter needs %zu bytes of signal buffers "
+                       "(%lld rows x %d columns, %d terms); its scratch holds %zu",
+                       need, static_cast<long long>(pl.R), chunk_width(num_cols), nt, cap);
+  }
   for (int32_t col0 = 0; col0 < num_cols;) {
     const int C = chunk_width(num_cols - col0);
     Scratch sc(st);
-    unsigned char *buf = nullptr;
-    GIFT_TRY(sc.get(&buf, chunk_buffer_bytes(pl, C), "filter signal buffers"));
+    unsigned char *buf = fixed_buf;
+    if (!buf) GIFT_TRY(sc.get(&buf, chunk_buffer_bytes(pl, C), "filter signal buffers"));
     ChunkBuffers bf;
     carve_chunk_buffers(pl, C, buf, &bf);
     GIFT_TRY(enqueue_filter_chunk(pl, bf, C, col0, st));
     col0 += C;
   }
   return GIFT_OK;
+}
+
+}  // namespace
+}  // namespace gift
+
+extern "C" gift_status gift_filter_placement(const gift_graph *g, const gift_term *terms,
+                                             int32_t nt, const void *x_in, int32_t num_cols,
+                                             int64_t ld_in, int32_t in_dt, void *y_out,
+                                             int64_t ld_out, int32_t out_dt,
+                                             const uint8_t *fixed, void *stream) {
+  clear_error();
+  return filter_impl(g, terms, nt, x_in, num_cols, ld_in, in_dt, y_out, ld_out, out_dt, fixed,
+                     stream, nullptr, 0);
+}
+
+extern "C" gift_status gift_filter_placement_noalloc(const gift_graph *g, const gift_term *terms,
+                                                     int32_t nt, const void *x_in,
+                                                     int32_t num_cols, int64_t ld_in,
+                                                     int32_t in_dt, void *y_out, int64_t ld_out,
+                                                     int32_t out_dt, const uint8_t *fixed,
+                                                     void *stream) {
+  clear_error();
+  void *p = nullptr;
+  GIFT_TRY(scratch_address(&p));
+  return filter_impl(g, terms, nt, x_in, num_cols, ld_in, in_dt, y_out, ld_out, out_dt, fixed,
+                     stream, static_cast<unsigned char *>(p), kNoAllocScratchBytes);
 }
 
 extern "C" gift_status gift_filter_exact(const gift_graph *g, double sigma, const void *x_in,
