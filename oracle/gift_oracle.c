@@ -533,3 +533,23 @@ int oracle_import_csr(int64_t num_rows, int64_t nnz, const int64_t *row_ptr,
   *out = g;
   return ORACLE_OK;
 }
+
+/* Density overflow of a bin-density map (the quantity placers track from the
+ * density of Section 2.2, eq. density_eq): the area by which bins exceed
+ * `target` times their own area, over the total object area,
+ *     sum_b max(0, rho_b - target * A_b) / total_area,
+ * A_b = ((xh - xl) / nbx) ((yh - yl) / nby), summed over the bins in row-major
+ * order. */
+int oracle_density_overflow(const double *density, int64_t nbx, int64_t nby, double xl,
+                            double yl, double xh, double yh, double target, double total_area,
+                            double *overflow) {
+  if (nbx < 1 || nby < 1 || !(xh > xl) || !(yh > yl) || !(total_area > 0.0)) return ORACLE_EINVAL;
+  double area = ((xh - xl) / (double)nbx) * ((yh - yl) / (double)nby);
+  double s = 0.0;
+  for (int64_t k = 0; k < nbx * nby; ++k) {
+    double e = density[k] - target * area;
+    if (e > 0.0) s = s + e;
+  }
+  *overflow = s / total_area;
+  return ORACLE_OK;
+}

@@ -47,6 +47,9 @@ def load(path: Optional[str] = None):
     lib.oracle_bin_density.argtypes = [i64, vp, vp, vp, C.c_double, C.c_double, C.c_double,
                                        C.c_double, i64, i64, vp]
     lib.oracle_bin_density.restype = C.c_int
+    lib.oracle_density_overflow.argtypes = [vp, i64, i64, C.c_double, C.c_double, C.c_double,
+                                            C.c_double, C.c_double, C.c_double, vp]
+    lib.oracle_density_overflow.restype = C.c_int
     lib.oracle_import_csr.argtypes = [i64, i64, vp, vp, vp, C.POINTER(vp)]
     lib.oracle_import_csr.restype = C.c_int
     if path is None:
@@ -224,3 +227,19 @@ def bin_density(x: np.ndarray, w, h, box, nbx: int, nby: int, lib=None) -> np.nd
     if rc:
         raise OracleError(f"oracle_bin_density failed ({rc})")
     return out
+
+
+def density_overflow(density: np.ndarray, box, target: float, total_area: float,
+                     lib=None) -> float:
+    """sum_b max(0, rho_b - target * bin area) / total_area of an nby x nbx
+    density map (see oracle_density_overflow)."""
+    lib = lib or load()
+    d = np.ascontiguousarray(density, dtype=np.float64)
+    nby, nbx = d.shape
+    out = np.zeros(1, dtype=np.float64)
+    rc = lib.oracle_density_overflow(_ptr(d), nbx, nby, float(box[0]), float(box[1]),
+                                     float(box[2]), float(box[3]), float(target),
+                                     float(total_area), _ptr(out))
+    if rc:
+        raise OracleError(f"oracle_density_overflow failed ({rc})")
+    return float(out[0])

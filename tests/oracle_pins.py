@@ -421,6 +421,18 @@ def pin_bin_density(lib):
                 ly = max(0.0, min(ys[1], (j + 1) * 20) - max(ys[0], j * 20))
                 ex[j, i] = lx * ly
         assert np.allclose(one, ex, rtol=1e-12, atol=1e-12)
+    # overflow: the 2 x 1 cell above covers two unit bins fully; at target
+    # 0.5 each exceeds by 0.5, over a total object area of 2
+    d = O.bin_density(np.array([[1.0, 1.5]]), 2.0, 1.0, (0, 0, 4, 4), 4, 4, lib=lib)
+    assert O.density_overflow(d, (0, 0, 4, 4), 0.5, 2.0, lib=lib) == 0.5
+    assert O.density_overflow(d, (0, 0, 4, 4), 1.0, 2.0, lib=lib) == 0.0
+    # two unit cells stacked on one bin of area 1: excess 1 at target 1
+    d = O.bin_density(np.array([[0.5, 0.5], [0.5, 0.5]]), 1.0, 1.0, (0, 0, 2, 2), 2, 2, lib=lib)
+    assert O.density_overflow(d, (0, 0, 2, 2), 1.0, 2.0, lib=lib) == 0.5
+    # bins of area 4 (8 x 8 region, 4 x 4 grid): target 0.25 allows one unit
+    d = np.zeros((4, 4))
+    d[2, 3] = 3.0
+    assert O.density_overflow(d, (0, 0, 8, 8), 0.25, 3.0, lib=lib) == 2.0 / 3.0
 
 
 def _path_netlist(cells):
