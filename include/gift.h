@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define GIFT_ABI_VERSION 1
+#define GIFT_ABI_VERSION 2
 
 typedef enum {
   GIFT_OK = 0,
@@ -334,8 +334,9 @@ gift_status gift_destroy_graph(gift_graph *graph, void *stream);
  *                  (eq. wire_eq).  Star nodes count at the mean of their cells,
  *                  which gives exactly the clique model's value, so S does not
  *                  depend on the star threshold (up to rounding).
- *   norm2[q]       sum_i g_i^2; S / norm2 is the Rayleigh quotient
- *                  (eq. smoothness_ray).
+ *   norm2[q]       sum_i g_i^2.
+ *   rayleigh[q]    S / norm2, the Rayleigh quotient of eq. smoothness_ray
+ *                  (0 for a zero column).
  *   hpwl[q]        sum over nets of (max - min) of g over the net's pins: the
  *                  half-perimeter wirelength the paper evaluates placements
  *                  with.  Needs the netlist: net_ptr int64[num_nets + 1] and
@@ -344,7 +345,8 @@ gift_status gift_destroy_graph(gift_graph *graph, void *stream);
  *
  *   x        device, N x num_cols (num_cols in [1, 128]), leading dimension
  *            ld, dtype F32 or F64.
- *   Any of smoothness / norm2 / hpwl may be NULL (host double[num_cols]);
+ *   Any of smoothness / norm2 / rayleigh / hpwl may be NULL (host
+ *   double[num_cols]);
  *   with hpwl NULL the netlist is not read.
  *
  * Sums are formed in a fixed order (deterministic).  Synchronises `stream`.
@@ -353,8 +355,8 @@ gift_status gift_destroy_graph(gift_graph *graph, void *stream);
 gift_status gift_evaluate_placement(const gift_graph *graph, const void *x, int32_t num_cols,
                                     int64_t ld, int32_t dtype, const int64_t *net_ptr,
                                     const int32_t *pin_cell, int64_t num_nets, int64_t num_pins,
-                                    double *smoothness, double *norm2, double *hpwl,
-                                    void *stream);
+                                    double *smoothness, double *norm2, double *rayleigh,
+                                    double *hpwl, void *stream);
 
 /*
  * gift_eigen_placement -- the eigenvector placement that Section 3.3.1
@@ -433,6 +435,27 @@ gift_status gift_bin_density(const void *x, int64_t num_objects, int64_t ld, int
                              double h0, double xl, double yl, double xh, double yh,
                              int32_t nbx, int32_t nby, double *density, void *stream);
 
+/*
+ * gift_density_overflow -- overflow of a bin-density map (the density of
+ * Section 2.2, eq. density_eq, as placers track it): the area by which bins
+ * exceed `target` times their own area, over the total object area,
+ *
+ *     sum_b max(0, rho_b - target * A_b) / total_area,
+ *     A_b = ((xh - xl) / nbx) ((yh - yl) / nby).
+ *
+ *   density      device float64[nby][nbx] as gift_bin_density writes it.
+ *   target       allowed fraction of a bin's area (finite).
+ *   total_area   total object area (> 0).
+ *   overflow     host double: the result.
+ *
+ * Summed in fixed ranges and then in range order (deterministic).
+ * Synchronises `stream`.  Errors: GIFT_EINVAL (NULL buffers, grid, region,
+ * total_area), GIFT_ENOMEM, GIFT_EDEVICE.
+ */
+gift_status gift_density_overflow(const double *density, int32_t nbx, int32_t nby, double xl,
+                                  double yl, double xh, double yh, double target,
+                                  double total_area, double *overflow, void *stream);
+
 /* ------------------------------------------------------------------------
  * Batched filtering: many resident graphs (designs of any sizes) filtered
  * with the same terms and column count by one launch sequence, captured
@@ -510,8 +533,9 @@ gift_status gift_batch_create(const gift_graph *const *graphs, int32_t num_graph
  * gift_batch_run -- filter every graph of the batch: uploads the per-graph
  * I/O pointers (io: host array of num_graphs entries, read during the call
  * only; they may change from run to run) and replays the captured graph on
- * `stream`.  Asynchronous.  Runs of one batch share its buffers, so they must
- * be ordered (same stream, or event-ordered).  Errors: GIFT_EINVAL (NULL
+ * `stream`.  Asynchronous.  Runs of one batch share its buffers: each run
+ * waits (on the device) for the previous run of the batch, whatever stream
+ * it was enqueued on.  Errors: GIFT_EINVAL (NULL
  * pointers, leading dimension < num_cols, wrong device), GIFT_EDEVICE.
  */
 gift_status gift_batch_run(gift_batch *batch, const gift_batch_io *io, void *stream);
@@ -667,9 +691,47 @@ gift_status gift_profile_collect(int32_t prof_class, int64_t *launches, double *
  * ----------------------------------------------------------------------*/
 
 /*
- * Device memory held by the library's caching allocator: every block it
- * obtained from the runtime (cached or in use) and the part in use by graphs,
- * batches and in-flight calls.  Blocks freed on a stream are reused only for
+ * The caller's device allocator, for callers that keep device memory under
+ * their own allocator and budget (e.g. a framework's caching allocator).
+ *
+ *   alloc(bytes, device, stream, ctx)   returns `bytes` of device memory on
+ *        `device` (the current device during the call) for work ordered on
+ *        `stream` (a hipStream_t as void*), aligned to at least 256 bytes,
+ *        or NULL on failure (the library then returns GIFT_ENOMEM).
+ *   free(ptr, bytes, device, stream, ctx)   releases a block alloc returned.
+ *        Stream-ordered: every use of the block is enqueued on `stream`
+ *        before this point (or ordered before it by an event), so the block
+ *        may be reused at once by later work on `stream`; reuse on another
+ *        stream must first wait for `stream` (synchronise it or wait on an
+ *        event recorded on it).
+ *   ctx  passed back unchanged.
+ *
+ * Both callbacks may be called from any host thread (the serving engine's
+ * threads included) and must be thread-safe; they must not call back into
+ * the library.
+ */
+typedef struct {
+  void *(*alloc)(size_t bytes, int32_t device, void *stream, void *ctx);
+  void (*free)(void *ptr, size_t bytes, int32_t device, void *stream, void *ctx);
+  void *ctx;
+} gift_allocator;
+
+/*
+ * gift_set_allocator -- every device allocation the library makes from now
+ * on (graphs, build and filter scratch, batches, servers, evaluators) comes
+ * from `allocator` (copied) instead of the library's caching allocator; NULL
+ * switches back to the cache.  A block is always returned to the allocator
+ * that provided it, so the switch may happen at any time.  Pinned host
+ * memory (a few small readback and staging slots per device) stays the
+ * library's own.  Errors: GIFT_EINVAL when alloc or free is NULL.
+ */
+gift_status gift_set_allocator(const gift_allocator *allocator);
+
+/*
+ * Device memory held by the library's caching allocator (every block it
+ * obtained from the runtime, cached or in use) and the device memory in use
+ * by graphs, batches and in-flight calls (from the cache or from the
+ * caller's allocator).  Blocks freed on a stream are reused only for
  * that stream, so the cache never needs a device synchronisation to reuse.
  */
 gift_status gift_memory_stats(int64_t *bytes_held, int64_t *bytes_in_use);

@@ -48,6 +48,14 @@ class CsrDesc(C.Structure):
     ]
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_int32, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_int32, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
+
+
 class Term(C.Structure):
     _fields_ = [("sigma", C.c_double), ("order", C.c_int32), ("reserved", C.c_int32),
                 ("alpha", C.c_double)]
@@ -187,7 +195,10 @@ SIGNATURES = {
     "gift_evaluate_placement": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int64,
                                           C.c_int32, C.c_void_p, C.c_void_p, C.c_int64,
                                           C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
-                                          C.c_void_p]),
+                                          C.c_void_p, C.c_void_p]),
+    "gift_density_overflow": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_double,
+                                        C.c_double, C.c_double, C.c_double, C.c_double,
+                                        C.c_double, C.POINTER(C.c_double), C.c_void_p]),
     "gift_graph_export": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.c_void_p]),
     "gift_graph_export_normalised": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p,
@@ -210,6 +221,7 @@ SIGNATURES = {
                                        C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "gift_memory_stats": (C.c_int, [C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "gift_release_cached_memory": (C.c_int, []),
+    "gift_set_allocator": (C.c_int, [C.POINTER(Allocator)]),
     "gift_status_string": (C.c_char_p, [C.c_int]),
     "gift_last_error": (C.c_char_p, []),
     "gift_abi_version": (C.c_int32, []),

@@ -6,6 +6,7 @@ for device memory and streams.
 from __future__ import annotations
 
 import ctypes as C
+import threading
 from typing import Iterable, Optional, Sequence, Tuple
 
 import numpy as np
@@ -303,11 +304,21 @@ def bin_density(x: torch.Tensor, box: Sequence[float], nbx: int, nby: int, *,
 
 
 def density_overflow(density: torch.Tensor, box: Sequence[float], target: float,
-                     total_area: float) -> float:
-    """sum_b max(0, rho_b - target * bin area) / total object area."""
+                     total_area: float, stream=None) -> float:
+    """sum_b max(0, rho_b - target * bin area) / total object area of a
+    density map from ``bin_density`` (computed by the library)."""
+    if not (isinstance(density, torch.Tensor) and density.is_cuda and density.dim() == 2
+            and density.dtype == torch.float64):
+        raise TypeError("density must be a 2-D float64 CUDA tensor")
+    density = density.contiguous()
     nby, nbx = density.shape
-    area = (box[2] - box[0]) / nbx * (box[3] - box[1]) / nby
-    return float(torch.clamp(density - target * area, min=0).sum().item() / total_area)
+    out = C.c_double()
+    L.check(L.lib().gift_density_overflow(_ptr(density), nbx, nby, float(box[0]), float(box[1]),
+                                          float(box[2]), float(box[3]), float(target),
+                                          float(total_area), C.byref(out),
+                                          _stream_handle(stream)),
+            "gift_density_overflow")
+    return out.value
 
 
 def evaluate_placement(graph: Graph, x: torch.Tensor, net_ptr=None, pin_cell=None,
@@ -326,6 +337,7 @@ def evaluate_placement(graph: Graph, x: torch.Tensor, net_ptr=None, pin_cell=Non
         raise ValueError("x rows != graph cells")
     S = np.zeros(c)
     n2 = np.zeros(c)
+    rq = np.zeros(c)
     h = np.zeros(c) if net_ptr is not None else None
     np_d = pc_d = None
     E = P = 0
@@ -338,9 +350,10 @@ def evaluate_placement(graph: Graph, x: torch.Tensor, net_ptr=None, pin_cell=Non
         P = pc_d.shape[0]
     L.check(L.lib().gift_evaluate_placement(graph.handle, _ptr(x), c, x.stride(0),
                                             TORCH_DTYPES[x.dtype], _ptr(np_d), _ptr(pc_d), E, P,
-                                            _ptr(S), _ptr(n2), _ptr(h), _stream_handle(stream)),
+                                            _ptr(S), _ptr(n2), _ptr(rq), _ptr(h),
+                                            _stream_handle(stream)),
             "gift_evaluate_placement")
-    out = {"smoothness": S, "norm2": n2, "rayleigh": S / np.where(n2 > 0, n2, 1.0)}
+    out = {"smoothness": S, "norm2": n2, "rayleigh": rq}
     if h is not None:
         out["hpwl"] = h
     return out
@@ -529,6 +542,77 @@ class Server:
                 self.close()
         except Exception:
             pass
+
+
+class TorchAllocator:
+    """The library's device allocator hook (gift_set_allocator) served by
+    torch's caching allocator, so library memory counts against torch's pool
+    and budget.  A block freed on a stream other than the one it was
+    allocated for is released only after that stream's queued work is done
+    (torch may reuse a freed block at once on its allocation stream)."""
+
+    def __init__(self):
+        self._lock = threading.Lock()
+        self._stream_of = {}
+        self.allocs = 0
+        self.frees = 0
+        self.live_bytes = 0
+
+        def _alloc(nbytes, device, stream, ctx):
+            try:
+                with torch.cuda.device(int(device)):
+                    p = torch.cuda.caching_allocator_alloc(int(nbytes), device=int(device),
+                                                           stream=int(stream or 0))
+            except Exception:  # pragma: no cover - reported as GIFT_ENOMEM
+                return None
+            with self._lock:
+                self._stream_of[p] = (int(stream or 0), int(device), int(nbytes))
+                self.allocs += 1
+                self.live_bytes += int(nbytes)
+            return p
+
+        def _free(ptr, nbytes, device, stream, ctx):
+            with self._lock:
+                a_stream, dev, size = self._stream_of.pop(ptr)
+                self.frees += 1
+                self.live_bytes -= size
+            s = int(stream or 0)
+            if s != a_stream:
+                with torch.cuda.device(dev):
+                    if s:
+                        torch.cuda.ExternalStream(s).synchronize()
+                    else:
+                        torch.cuda.synchronize(dev)
+            torch.cuda.caching_allocator_delete(ptr)
+
+        self._fns = (L.ALLOC_FN(_alloc), L.FREE_FN(_free))
+        self.struct = L.Allocator(self._fns[0], self._fns[1], None)
+
+
+_ALLOCATOR = None
+
+
+def set_allocator(allocator) -> None:
+    """Route the library's device allocations to ``allocator`` (an object with
+    a ``struct`` field of type ``_lib.Allocator`` whose callbacks it keeps
+    alive, e.g. ``TorchAllocator()``); None switches back to the library's
+    own cache.  Blocks always go back to the allocator that provided them."""
+    global _ALLOCATOR
+    if allocator is None:
+        L.check(L.lib().gift_set_allocator(None), "gift_set_allocator")
+    else:
+        L.check(L.lib().gift_set_allocator(C.byref(allocator.struct)), "gift_set_allocator")
+    # keep the callbacks alive while the library may call them; the previous
+    # allocator stays referenced too (its blocks are returned to it later)
+    _ALLOCATOR = (allocator, _ALLOCATOR)
+
+
+def use_torch_allocator(on: bool = True) -> Optional[TorchAllocator]:
+    """Serve the library's device memory from torch's caching allocator (on)
+    or from the library's own cache (off)."""
+    a = TorchAllocator() if on else None
+    set_allocator(a)
+    return a
 
 
 def profile_enable(on: bool = True):

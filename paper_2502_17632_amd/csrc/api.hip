@@ -37,7 +37,8 @@ gift_status check_launch(const char *what) {
 
 namespace {
 
-// Stream-ordered caching allocator.  Device memory comes from hipMalloc in
+// Stream-ordered caching allocator, or the caller's allocator when one is set
+// (gift_set_allocator).  Device memory comes from hipMalloc in
 // blocks that are never returned to the runtime while cached: a freed block
 // goes back to the free list of the stream it was freed on and is handed out
 // again only for work on that same stream, so stream order alone makes the
@@ -50,13 +51,24 @@ struct Block {
   size_t size;
 };
 
+// A block in use: its size, device, and whether the caller's allocator
+// (rather than the cache) provided it, with that allocator's callbacks.
+struct Live {
+  size_t size;
+  int device;
+  bool hooked;
+  gift_allocator hook;
+};
+
 struct Pool {
   std::mutex m;
   // per (device, stream): free blocks by size
   std::map<std::pair<int, hipStream_t>, std::multimap<size_t, void *>> free_lists;
-  std::unordered_map<void *, std::pair<size_t, int>> live;  // ptr -> (size, device)
-  int64_t bytes_held = 0;   // all blocks, cached or in use
-  int64_t bytes_in_use = 0;
+  std::unordered_map<void *, Live> live;
+  int64_t bytes_held = 0;    // cached blocks and blocks in use from the cache
+  int64_t bytes_in_use = 0;  // every block in use, cache or caller's allocator
+  bool hook_set = false;
+  gift_allocator hook{};
 };
 
 Pool &pool() {
@@ -78,17 +90,35 @@ gift_status dev_alloc(void **p, size_t bytes, hipStream_t s, const char *what) {
   int dev = 0;
   (void)hipGetDevice(&dev);
   Pool &pl = pool();
+  gift_allocator hook{};
+  bool hooked = false;
   {
     std::lock_guard<std::mutex> lk(pl.m);
-    auto &fl = pl.free_lists[{dev, s}];
-    auto it = fl.lower_bound(need);
-    if (it != fl.end() && it->first <= need + need / 4) {
-      *p = it->second;
-      pl.live[it->second] = {it->first, dev};
-      pl.bytes_in_use += static_cast<int64_t>(it->first);
-      fl.erase(it);
-      return GIFT_OK;
+    hooked = pl.hook_set;
+    hook = pl.hook;
+    if (!hooked) {
+      auto &fl = pl.free_lists[{dev, s}];
+      auto it = fl.lower_bound(need);
+      if (it != fl.end() && it->first <= need + need / 4) {
+        *p = it->second;
+        pl.live[it->second] = Live{it->first, dev, false, {}};
+        pl.bytes_in_use += static_cast<int64_t>(it->first);
+        fl.erase(it);
+        return GIFT_OK;
+      }
     }
+  }
+  if (hooked) {
+    // the caller's allocator, called outside the lock
+    void *q = hook.alloc(need, dev, s, hook.ctx);
+    if (!q)
+      return set_error(GIFT_ENOMEM, "the caller's allocator returned NULL for %zu bytes (%s)",
+                       need, what);
+    std::lock_guard<std::mutex> lk(pl.m);
+    pl.live[q] = Live{need, dev, true, hook};
+    pl.bytes_in_use += static_cast<int64_t>(need);
+    *p = q;
+    return GIFT_OK;
   }
   hipError_t e = hipMalloc(p, need);
   if (e != hipSuccess) {
@@ -106,7 +136,7 @@ gift_status dev_alloc(void **p, size_t bytes, hipStream_t s, const char *what) {
                      hipGetErrorString(e));
   }
   std::lock_guard<std::mutex> lk(pl.m);
-  pl.live[*p] = {need, dev};
+  pl.live[*p] = Live{need, dev, false, {}};
   pl.bytes_held += static_cast<int64_t>(need);
   pl.bytes_in_use += static_cast<int64_t>(need);
   return GIFT_OK;
@@ -115,14 +145,34 @@ gift_status dev_alloc(void **p, size_t bytes, hipStream_t s, const char *what) {
 void dev_free(void *p, hipStream_t s) {
   if (!p) return;
   Pool &pl = pool();
+  Live lv{};
+  {
+    std::lock_guard<std::mutex> lk(pl.m);
+    auto it = pl.live.find(p);
+    if (it == pl.live.end()) return;
+    lv = it->second;
+    pl.live.erase(it);
+    pl.bytes_in_use -= static_cast<int64_t>(lv.size);
+    if (!lv.hooked) {
+      pl.free_lists[{lv.device, s}].emplace(lv.size, p);
+      return;
+    }
+  }
+  // back to the allocator that provided it, outside the lock
+  lv.hook.free(p, lv.size, lv.device, s, lv.hook.ctx);
+}
+
+gift_status set_allocator(const gift_allocator *a) {
+  Pool &pl = pool();
   std::lock_guard<std::mutex> lk(pl.m);
-  auto it = pl.live.find(p);
-  if (it == pl.live.end()) return;
-  const size_t size = it->second.first;
-  const int dev = it->second.second;
-  pl.live.erase(it);
-  pl.bytes_in_use -= static_cast<int64_t>(size);
-  pl.free_lists[{dev, s}].emplace(size, p);
+  if (a) {
+    pl.hook = *a;
+    pl.hook_set = true;
+  } else {
+    pl.hook = gift_allocator{};
+    pl.hook_set = false;
+  }
+  return GIFT_OK;
 }
 
 gift_status release_cached(int dev) {
@@ -295,6 +345,13 @@ gift_status gift_memory_stats(int64_t *bytes_held, int64_t *bytes_in_use) {
   clear_error();
   pool_stats(bytes_held, bytes_in_use);
   return GIFT_OK;
+}
+
+gift_status gift_set_allocator(const gift_allocator *allocator) {
+  clear_error();
+  if (allocator && (!allocator->alloc || !allocator->free))
+    return set_error(GIFT_EINVAL, "gift_set_allocator: alloc and free must both be set");
+  return set_allocator(allocator);
 }
 
 gift_status gift_release_cached_memory(void) {

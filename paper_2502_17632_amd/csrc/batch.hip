@@ -664,6 +664,9 @@ extern "C" gift_status gift_batch_run(gift_batch *b, const gift_batch_io *io, vo
   }
   if (b->cells == 0) return GIFT_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
+  // the table and the signal buffers are shared by every run: order this run
+  // after the previous one, which may have been enqueued on another stream
+  GIFT_HIP(hipStreamWaitEvent(st, b->last_run, 0));
   GIFT_TRY(upload_table(b, io, st));
   GIFT_HIP(hipGraphLaunch(b->exec, st));
   GIFT_HIP(hipEventRecord(b->last_run, st));

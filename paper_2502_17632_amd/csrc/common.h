@@ -79,6 +79,8 @@ void dev_free(void *p, hipStream_t s);
 // Returns the cached (free) blocks of device `dev` (all devices if < 0) to
 // the runtime; synchronises the device first.
 gift_status release_cached(int dev);
+// Routes later allocations to the caller's allocator (NULL: the cache).
+gift_status set_allocator(const gift_allocator *a);
 void pool_stats(int64_t *held, int64_t *in_use);
 
 // Host readback of a few device scalars without a copy: a slot of

@@ -69,10 +69,70 @@ __global__ void k_density_out(const unsigned long long *acc, int64_t nb, double 
   if (k < nb) out[k] = static_cast<double>(acc[k]) / kFixScale * area;
 }
 
+// Overflow partial sums: block b sums max(0, rho_k - cap) over its fixed
+// range of bins (a block tree of fixed shape), part[b].
+constexpr int kOverflowBlocks = 256;
+__global__ __launch_bounds__(kBlock) void k_overflow_part(const double *density, int64_t nb,
+                                                          double cap, double *part) {
+  __shared__ double red[kBlock];
+  const int64_t per = (nb + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = static_cast<int64_t>(blockIdx.x) * per;
+  const int64_t hi = lo + per < nb ? lo + per : nb;
+  double s = 0.0;
+  for (int64_t k = lo + threadIdx.x; k < hi; k += kBlock) {
+    const double e = density[k] - cap;
+    if (e > 0.0) s += e;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// out = (sum of part in block order) / total_area
+__global__ void k_overflow_total(const double *part, int nparts, double total_area,
+                                 double *out) {
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int b = 0; b < nparts; ++b) s += part[b];
+  out[0] = s / total_area;
+}
+
 }  // namespace
 }  // namespace gift
 
 using namespace gift;
+
+extern "C" gift_status gift_density_overflow(const double *density, int32_t nbx, int32_t nby,
+                                             double xl, double yl, double xh, double yh,
+                                             double target, double total_area,
+                                             double *overflow, void *stream) {
+  clear_error();
+  if (!density || !overflow) return set_error(GIFT_EINVAL, "gift_density_overflow: NULL buffer");
+  if (nbx < 1 || nby < 1 || static_cast<int64_t>(nbx) * nby > (int64_t(1) << 28))
+    return set_error(GIFT_EINVAL, "bin grid %d x %d", nbx, nby);
+  if (!(xh > xl) || !(yh > yl) || !std::isfinite(xh - xl) || !std::isfinite(yh - yl))
+    return set_error(GIFT_EINVAL, "empty or infinite placement region");
+  if (!(total_area > 0.0) || !std::isfinite(total_area) || !std::isfinite(target))
+    return set_error(GIFT_EINVAL, "total_area must be finite and > 0, target finite");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t nb = static_cast<int64_t>(nbx) * nby;
+  const double cap = target * (((xh - xl) / nbx) * ((yh - yl) / nby));
+  Scratch sc(st);
+  double *part = nullptr;
+  GIFT_TRY(sc.get(&part, kOverflowBlocks + 1, "overflow partial sums"));
+  k_overflow_part<<<kOverflowBlocks, kBlock, 0, st>>>(density, nb, cap, part);
+  GIFT_TRY(check_launch("k_overflow_part"));
+  k_overflow_total<<<1, kWave, 0, st>>>(part, kOverflowBlocks, total_area, part + kOverflowBlocks);
+  GIFT_TRY(check_launch("k_overflow_total"));
+  GIFT_HIP(hipMemcpyAsync(overflow, part + kOverflowBlocks, sizeof(double), hipMemcpyDeviceToHost,
+                          st));
+  GIFT_HIP(hipStreamSynchronize(st));
+  return GIFT_OK;
+}
 
 extern "C" gift_status gift_bin_density(const void *x, int64_t num_objects, int64_t ld,
                                         int32_t dtype, const double *widths,

@@ -4,7 +4,7 @@
 //            wirelength of Section 2.2 (eq. wire_eq); with star nodes placed
 //            at the mean of their cells, a star contributes exactly what its
 //            clique would, so S is the clique-model value for any threshold;
-//   |g|^2  per column, so S / |g|^2 is the Rayleigh quotient
+//   |g|^2  per column, and R(g) = S / |g|^2, the Rayleigh quotient
 //            (eq. smoothness_ray);
 //   HPWL   = sum over nets of max - min of g over the net's pins.
 // Everything is float64.  Sums are formed per row tile (S) or per block of
@@ -139,6 +139,15 @@ __global__ void k_eval_reduce(const double *part, int64_t nb, int32_t stride, in
   out[k] = s;
 }
 
+// res[3C + q] = S / |g|^2 (the Rayleigh quotient of eq. smoothness_ray), 0
+// for a zero signal.
+__global__ void k_eval_rayleigh(double *res, int32_t C) {
+  const int q = threadIdx.x;
+  if (q >= C) return;
+  const double n2 = res[C + q];
+  res[3 * C + q] = n2 > 0.0 ? res[q] / n2 : 0.0;
+}
+
 }  // namespace
 }  // namespace gift
 
@@ -148,8 +157,8 @@ extern "C" gift_status gift_evaluate_placement(const gift_graph *g, const void *
                                                int32_t num_cols, int64_t ld, int32_t dtype,
                                                const int64_t *net_ptr, const int32_t *pin_cell,
                                                int64_t num_nets, int64_t num_pins,
-                                               double *smoothness,
-                                               double *norm2, double *hpwl, void *stream) {
+                                               double *smoothness, double *norm2,
+                                               double *rayleigh, double *hpwl, void *stream) {
   clear_error();
   if (!g) return set_error(GIFT_EINVAL, "gift_evaluate_placement: NULL graph");
   if (num_cols < 1 || num_cols > 128) return set_error(GIFT_EINVAL, "num_cols %d not in [1, 128]", num_cols);
@@ -165,8 +174,8 @@ extern "C" gift_status gift_evaluate_placement(const gift_graph *g, const void *
   Scratch sc(st);
   double *vx = nullptr, *res = nullptr;
   GIFT_TRY(sc.get(&vx, (V > 0 ? V : 1) * C, "star means"));
-  GIFT_TRY(sc.get(&res, 3 * C, "metrics"));
-  GIFT_HIP(hipMemsetAsync(res, 0, sizeof(double) * 3 * C, st));
+  GIFT_TRY(sc.get(&res, 4 * C, "metrics"));
+  GIFT_HIP(hipMemsetAsync(res, 0, sizeof(double) * 4 * C, st));
   const int64_t T = g->num_tiles[0];
   if (V > 0) {
     k_eval_star_means<<<grid_for(V * kWave), kBlock, 0, st>>>(g->row_ptr, g->col, N, V, x, ld,
@@ -192,12 +201,15 @@ extern "C" gift_status gift_evaluate_placement(const gift_graph *g, const void *
     k_eval_reduce<<<1, C, 0, st>>>(part, nb, C, C, res + 2 * C);
     GIFT_TRY(check_launch("k_eval_reduce"));
   }
-  std::vector<double> h(3 * C);
-  GIFT_HIP(hipMemcpyAsync(h.data(), res, sizeof(double) * 3 * C, hipMemcpyDeviceToHost, st));
+  k_eval_rayleigh<<<1, C, 0, st>>>(res, C);
+  GIFT_TRY(check_launch("k_eval_rayleigh"));
+  std::vector<double> h(4 * C);
+  GIFT_HIP(hipMemcpyAsync(h.data(), res, sizeof(double) * 4 * C, hipMemcpyDeviceToHost, st));
   GIFT_HIP(hipStreamSynchronize(st));
   for (int32_t q = 0; q < C; ++q) {
     if (smoothness) smoothness[q] = h[q];
     if (norm2) norm2[q] = h[C + q];
+    if (rayleigh) rayleigh[q] = h[3 * C + q];
     if (hpwl) hpwl[q] = h[2 * C + q];
   }
   return GIFT_OK;

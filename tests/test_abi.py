@@ -37,7 +37,7 @@ def test_every_declared_symbol_has_a_binding_signature():
 
 def test_abi_version_and_status_strings():
     lib = L.lib()
-    assert lib.gift_abi_version() == 1
+    assert lib.gift_abi_version() == 2
     for s in range(6):
         assert lib.gift_status_string(s).startswith(b"GIFT_")
     assert b"unknown" in lib.gift_status_string(99)
@@ -47,7 +47,7 @@ STRUCTS = {"gift_graph_desc": L.GraphDesc, "gift_csr_desc": L.CsrDesc, "gift_ter
            "gift_batch_io": L.BatchIO, "gift_batch_info": L.BatchInfo,
            "gift_server_config": L.ServerConfig, "gift_request": L.Request,
            "gift_request_result": L.RequestResult, "gift_server_stats": L.ServerStats,
-           "gift_eigen_result": L.EigenResult}
+           "gift_eigen_result": L.EigenResult, "gift_allocator": L.Allocator}
 
 
 def c_layouts(tmp_path):
@@ -194,7 +194,7 @@ def test_evaluate_arguments_rejected_without_device_work():
     lib = L.lib()
     out = (C.c_double * 2)()
     assert lib.gift_evaluate_placement(None, None, 2, 2, 0, None, None, 0, 0, out, None, None,
-                                       None) == L.GIFT_EINVAL
+                                       None, None) == L.GIFT_EINVAL
 
 
 def test_eigen_arguments_rejected_without_device_work():
@@ -239,3 +239,24 @@ def test_host_csr_row_ptr_checked_before_device_work():
         out = C.c_void_p()
         assert lib.gift_graph_import_csr(C.byref(d), None, C.byref(out)) == L.GIFT_EINVAL
     assert lib.gift_graph_import_csr(None, None, C.byref(out)) == L.GIFT_EINVAL
+
+
+def test_allocator_needs_both_callbacks():
+    lib = L.lib()
+    a = L.Allocator()
+    assert lib.gift_set_allocator(C.byref(a)) == L.GIFT_EINVAL
+    assert lib.gift_set_allocator(None) == L.GIFT_OK
+
+
+def test_density_overflow_arguments_rejected_without_device_work():
+    lib = L.lib()
+    out = C.c_double()
+    buf = (C.c_double * 4)()
+    assert lib.gift_density_overflow(None, 2, 2, 0, 0, 1, 1, 1.0, 1.0, C.byref(out),
+                                     None) == L.GIFT_EINVAL
+    assert lib.gift_density_overflow(buf, 0, 2, 0, 0, 1, 1, 1.0, 1.0, C.byref(out),
+                                     None) == L.GIFT_EINVAL
+    assert lib.gift_density_overflow(buf, 2, 2, 0, 0, 1, 1, 1.0, 0.0, C.byref(out),
+                                     None) == L.GIFT_EINVAL
+    assert lib.gift_density_overflow(buf, 2, 2, 1, 0, 1, 1, 1.0, 1.0, C.byref(out),
+                                     None) == L.GIFT_EINVAL

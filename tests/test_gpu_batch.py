@@ -108,6 +108,33 @@ def test_graph_replays_match_eager_with_work_in_between(designs):
     b.close()
 
 
+def test_runs_on_two_streams_in_a_row(designs):
+    """Two runs of one batch enqueued back to back on two different streams,
+    with different inputs and no host synchronisation between them: the
+    second waits for the first (they share the batch's buffers), so each
+    result equals filtering its own inputs alone, bit for bit."""
+    import torch
+    import paper_2502_17632_amd as gift
+    nls, xs = designs
+    graphs = build_all(nls, "f32", [4.0])
+    b = gift.Batch(graphs, *EQ4, num_cols=8, tune=0)
+    rng = np.random.default_rng(9)
+    inputs = [[to_dev(x + rng.normal(0, 5.0, size=x.shape), torch.float32) for x in xs]
+              for _ in range(2)]
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    ys1 = b.run(inputs[0], stream=s1)
+    ys2 = b.run(inputs[1], stream=s2)
+    torch.cuda.synchronize()
+    for rep, ys in enumerate((ys1, ys2)):
+        alone = [gift.filter_placement(g, *EQ4, x) for g, x in zip(graphs, inputs[rep])]
+        torch.cuda.synchronize()
+        for i, (y, a) in enumerate(zip(ys, alone)):
+            assert torch.equal(y, a), f"run {rep} on its own stream, design {i}"
+    log("[batch] runs on two streams in a row equal to eager")
+    b.close()
+
+
 def test_batch_outputs_in_place_and_fixed_rows(designs, oracles):
     """Caller-provided outputs with a leading dimension, fixed masks on some
     designs, float64 input."""

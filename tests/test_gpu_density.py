@@ -54,6 +54,10 @@ def test_density_of_the_filtered_medium_placement():
         assert np.allclose(d.cpu().numpy(), ref, rtol=1e-12, atol=tol), \
             np.abs(d.cpu().numpy() - ref).max()
         over = gift.density_overflow(d, box, 1.0, float(nl.num_cells))
+        ref_over = O.density_overflow(ref, box, 1.0, float(nl.num_cells))
+        # each bin of the map may differ by tol; the overflow by at most
+        # (bins) * tol / total area
+        assert abs(over - ref_over) <= 64 * 64 * tol / nl.num_cells + 1e-12, (over, ref_over)
         log(f"[density] {name}: max {d.max().item():.1f} of bin area "
             f"{(1000 / 64) ** 2:.1f}, overflow at target 1: {over:.4f}")
     g.close()

@@ -40,6 +40,7 @@ def test_metrics_match_the_oracle_before_and_after_filtering(dtype):
             f"R {m['rayleigh']}")
         assert np.all(rel(m["smoothness"], S) < TOL), (name, m["smoothness"], S)
         assert np.all(rel(m["norm2"], n2) < TOL)
+        assert np.all(rel(m["rayleigh"], S / n2) < TOL)  # eq. smoothness_ray
         assert np.all(rel(m["hpwl"], h) < TOL)
     # the low-pass filter smooths a white-noise signal (Section 3.1): the
     # Rayleigh quotient drops.  (A placement whose fixed cells sit on the die
