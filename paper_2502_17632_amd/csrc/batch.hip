@@ -194,10 +194,26 @@ void use_schedule(gift_batch *b, const Candidate &cand) {
   pl.final_tile_graph = b->ftile_graph[c];
   pl.num_final_tiles = b->num_ftiles[c];
   b->chunks = chunk_list(b->num_cols, cand.chunk);
+  // each graph's tiles in the all-rows list of this class (the table is
+  // uploaded with the next run)
+  const size_t ng = b->graphs.size();
+  int64_t t = 0;
+  for (size_t g = 0; g < ng; ++g) {
+    const int64_t n = b->graphs[g]->num_tiles[c];
+    for (size_t k = 0; k < b->table.size() / ng; ++k) {
+      b->table[k * ng + g].tile_lo = static_cast<int32_t>(t);
+      b->table[k * ng + g].tile_hi = static_cast<int32_t>(t + n);
+    }
+    t += n;
+  }
 }
 
+// Buffers for the widest chunk of any schedule: the centring partial sums
+// grow with the tile count, so size them for the class with the most tiles.
 size_t buffers_for(const gift_batch *b, int widest) {
-  return chunk_buffer_bytes(b->plan, chunk_width(std::min(widest, b->num_cols)));
+  FilterPlan pl = b->plan;
+  pl.num_tiles = std::max(b->num_tiles[0], b->num_tiles[1]);
+  return chunk_buffer_bytes(pl, chunk_width(std::min(widest, b->num_cols)));
 }
 
 // Enqueues the whole filter (every column chunk) of the current schedule.
@@ -316,6 +332,7 @@ gift_status autotune(gift_batch *b, Candidate *best) {
   b->info.num_candidates = static_cast<int32_t>(cands.size());
   for (size_t i = 0; i < cands.size(); ++i) {
     use_schedule(b, cands[i]);
+    GIFT_TRY(upload_table(b, io.data(), b->home));
     GIFT_TRY(capture(b));
     double ms = 0;
     GIFT_TRY(time_replays(b, 3, &ms));
@@ -380,9 +397,17 @@ size_t dynamic_batch_bytes(const gift_graph *const *graphs, int32_t n, int32_t s
   // every term but one may keep a saved iterate
   const size_t rb = dtype_size(storage) * static_cast<size_t>(chunk_width(num_cols)) *
                     static_cast<size_t>(pl.R);
+  // centring partial sums and multipliers (16-bit storage)
+  const size_t C = static_cast<size_t>(chunk_width(num_cols));
+  const size_t centre =
+      centred_storage(storage)
+          ? sizeof(double) * ((static_cast<size_t>(tiles) + 1) * (C + num_terms) +
+                              static_cast<size_t>(n) * num_terms * C) + 512
+          : 0;
   return (3 + static_cast<size_t>(num_terms)) * (rb + 256) +
          static_cast<size_t>(tiles) * (sizeof(TileDesc) + 4) +
-         static_cast<size_t>(n) * (kMaxTerms * sizeof(GraphDev) + 2 * sizeof(ConcatSrc)) + 4096;
+         static_cast<size_t>(n) * (kMaxTerms * sizeof(GraphDev) + 2 * sizeof(ConcatSrc)) + 4096 +
+         centre;
 }
 
 gift_status enqueue_dynamic_batch(const gift_graph *const *graphs, const GraphIO *ios, int32_t n,
@@ -405,8 +430,11 @@ gift_status enqueue_dynamic_batch(const gift_graph *const *graphs, const GraphIO
       return set_error(GIFT_EINVAL, "graph %d: storage differs from graph 0", g);
     GraphIO io = ios[g];
     io.num_cells = gr->num_cells;
+    const int32_t tlo = static_cast<int32_t>(pl.num_tiles);
+    const int32_t thi = static_cast<int32_t>(pl.num_tiles + gr->num_tiles[c]);
     for (size_t k = 0; k < ngr; ++k)
-      table[k * n + g] = GraphDev{gr->row_ptr, gr->col, per[g][k].val, per[g][k].diag, pl.R, io};
+      table[k * n + g] = GraphDev{gr->row_ptr, gr->col, per[g][k].val, per[g][k].diag, pl.R, io,
+                                  gr->deg, tlo, thi};
     if (gr->num_tiles[c] > 0) {
       sa.push_back(ConcatSrc{gr->tiles[c], gr->num_tiles[c], pl.num_tiles, g});
       pl.num_tiles += gr->num_tiles[c];
@@ -465,6 +493,8 @@ gift_status enqueue_dynamic_batch(const gift_graph *const *graphs, const GraphIO
   pl.tile_graph = ga;
   pl.final_tiles = tf;
   pl.final_tile_graph = gf;
+  pl.centre = centred_storage(pl.storage);
+  pl.num_graphs = n;
   pl.groups = per[0];
   for (size_t k = 0; k < ngr; ++k) pl.groups[k].graphs = dtable + k * n;
   pl.terms = terms;
@@ -546,7 +576,8 @@ extern "C" gift_status gift_batch_create(const gift_graph *const *graphs, int32_
     for (size_t k = 0; k < ngr; ++k)
       b->table[k * num_graphs + g] =
           GraphDev{gr->row_ptr, gr->col, per[g][k].val, per[g][k].diag, row_off,
-                   GraphIO{nullptr, num_cols, nullptr, num_cols, nullptr, gr->num_cells}};
+                   GraphIO{nullptr, num_cols, nullptr, num_cols, nullptr, gr->num_cells},
+                   gr->deg, 0, 0};
     row_off += gr->num_rows;
     b->nnz += gr->nnz;
     b->cells += gr->num_cells;
@@ -589,6 +620,8 @@ extern "C" gift_status gift_batch_create(const gift_graph *const *graphs, int32_
 
   FilterPlan &pl = b->plan;
   pl.storage = b->storage;
+  pl.centre = centred_storage(b->storage);
+  pl.num_graphs = num_graphs;
   pl.R = b->R;
   pl.nnz = b->nnz;
   pl.cell_rows = b->cells;

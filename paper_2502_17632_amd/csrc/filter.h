@@ -22,7 +22,9 @@ struct GraphIO {
 
 // One graph of a launch, for one sigma: its CSR (graph-local row and column
 // indices), the normalised values of that sigma, where its rows start in the
-// launch's signal buffers, and its I/O.
+// launch's signal buffers, and its I/O.  deg and the tile range (the graph's
+// tiles in the launch's all-rows tile list) serve the centring of 16-bit
+// signals.
 struct GraphDev {
   const int32_t *row_ptr;
   const int32_t *col;
@@ -30,6 +32,8 @@ struct GraphDev {
   const void *diag;
   int64_t row_off;
   GraphIO io;
+  const double *deg;
+  int32_t tile_lo, tile_hi;
 };
 
 struct PlanGroup {
@@ -61,13 +65,25 @@ struct FilterPlan {
   int32_t num_terms = 0;
   int32_t in_dtype = GIFT_F32, out_dtype = GIFT_F32;
   bool profile = true;  // bracket passes with profiler events
+  // 16-bit storage: the iterates hold x - c v_sigma (v_sigma = sqrt(d + sigma),
+  // the eigenvector of A~_sigma with eigenvalue 1), c per graph, group and
+  // column; the final combine adds c v_sigma back.
+  bool centre = false;
+  int64_t num_graphs = 1;
 };
 
 // Signal buffers of one column chunk: [R][C] storage-type rows.
 struct ChunkBuffers {
   void *x0 = nullptr, *ping = nullptr, *pong = nullptr;
   void *saved[kMaxTerms] = {};  // NULL for the term the last pass forms
+  double *centre_part = nullptr;  // [tiles][C + groups] partial sums (centring)
+  double *centre = nullptr;       // [graphs][groups][C] multipliers c (centring)
 };
+
+// Whether filters of this storage type centre their signal (16-bit types).
+inline bool centred_storage(int32_t storage) {
+  return storage == GIFT_BF16 || storage == GIFT_F16;
+}
 
 // Widest supported chunk (16, 8, 4, 2, 1) not above `remaining`.
 int chunk_width(int remaining);

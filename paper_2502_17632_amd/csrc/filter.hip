@@ -57,6 +57,8 @@ struct LaunchArgs {
   const int32_t *tile_graph;
   const GraphDev *graphs;
   GraphDev one;
+  // centring multipliers [graphs][groups][C] (16-bit storage), else NULL
+  double *centre;
 };
 
 template <bool kBatch>
@@ -65,12 +67,23 @@ __device__ __forceinline__ GraphDev graph_of(const LaunchArgs &l, uint32_t tile)
   else return l.one;
 }
 
+template <bool kBatch>
+__device__ __forceinline__ uint32_t graph_index(const LaunchArgs &l, uint32_t tile) {
+  if constexpr (kBatch) return static_cast<uint32_t>(to_global(l.tile_graph)[tile]);
+  else return 0;
+}
+
 struct FinalArgs {
   int32_t num_terms;
   int32_t in_dtype, out_dtype;
   int32_t col0;  // first column of this chunk in the caller's matrices
   const void *src[kMaxTerms];  // saved iterate of each term; NULL = this pass
   double alpha[kMaxTerms];
+  // centring: each term's sigma group and sigma (the term's iterate holds
+  // x - c v_sigma; the combine adds c v_sigma back)
+  int32_t num_groups;
+  int32_t term_group[kMaxTerms];
+  double term_sigma[kMaxTerms];
 };
 
 // Writes local row `lr` of the pass result: the stored iterate, or (last
@@ -78,7 +91,8 @@ struct FinalArgs {
 template <int D, int C, bool kFinal>
 __device__ __forceinline__ void emit_row(const FinalArgs &f, const GraphDev &gd,
                                          typename Store<D>::T *y, int64_t lr,
-                                         const typename Store<D>::A *acc) {
+                                         const typename Store<D>::A *acc,
+                                         const double *cen = nullptr) {
   using S = Store<D>;
   using T = typename S::T;
   if constexpr (!kFinal) {
@@ -96,10 +110,12 @@ __device__ __forceinline__ void emit_row(const FinalArgs &f, const GraphDev &gd,
       if (fixed) {
         s = load_in(io.x_in, f.in_dtype, lr * io.ld_in + f.col0 + c);
       } else {
+        const double dl = cen ? to_global(gd.deg)[lr] : 0.0;
         for (int t = 0; t < f.num_terms; ++t) {
           const T *src = static_cast<const T *>(f.src[t]);
           double v = src ? static_cast<double>(S::load(to_global(src)[srow * C + c]))
                          : static_cast<double>(acc[c]);
+          if (cen) v = v + to_global(cen)[f.term_group[t] * C + c] * sqrt(dl + f.term_sigma[t]);
           s = s + f.alpha[t] * v;
         }
       }
@@ -151,6 +167,10 @@ __global__ __launch_bounds__(kBlock) void k_spmm(LaunchArgs l, const void *xin, 
   const int32_t r0 = td.r0, r1 = td.r1, p0 = td.p0, p1 = td.p1;
   const int nrows = r1 - r0;
   const int n = p1 - p0;
+  const double *cen = kFinal && l.centre
+                          ? l.centre + static_cast<int64_t>(graph_index<kBatch>(l, tile)) *
+                                           f.num_groups * C
+                          : nullptr;
   const T *x = static_cast<const T *>(xin) + gd.row_off * C;
   T *y = kFinal ? nullptr : static_cast<T *>(yout) + gd.row_off * C;
   const gptr<const T> val = to_global(static_cast<const T *>(gd.val));
@@ -202,7 +222,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm(LaunchArgs l, const void *xin, 
         for (int w = 1; w < kBlock / kWave; ++w) s += lred[w][c];
         tot[c] = s + dg * S::load(xi.v[c]);
       }
-      emit_row<D, C, kFinal>(f, gd, y, r0, tot);
+      emit_row<D, C, kFinal>(f, gd, y, r0, tot, cen);
     }
     return;
   }
@@ -323,7 +343,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm(LaunchArgs l, const void *xin, 
 #pragma unroll
         for (int c = 0; c < C; ++c) acc[c] = acc[c] + dg * S::load(xi.v[c]);
       }
-      emit_row<D, C, kFinal>(f, gd, y, r0 + rr, acc);
+      emit_row<D, C, kFinal>(f, gd, y, r0 + rr, acc, cen);
     }
   }
 }
@@ -331,9 +351,13 @@ __global__ __launch_bounds__(kBlock) void k_spmm(LaunchArgs l, const void *xin, 
 // x0 for the rows of one tile: cell rows are the caller's signal rounded to
 // the storage type, star rows the float64 mean of their net's cells (a
 // group of lanes per star row).  A tile never mixes cell rows and star rows.
+//
+// Centred (l.centre != NULL, 16-bit storage): every row stores x - c v with
+// v = sqrt(d + sigma) of this sigma group and c = l.centre[graph][grp][col].
 template <int D, int C, bool kBatch>
 __global__ __launch_bounds__(kBlock) void k_prep(LaunchArgs l, int32_t in_dtype, int32_t col0,
-                                                 void *x0v) {
+                                                 void *x0v, int32_t grp, int32_t groups,
+                                                 double sigma) {
   const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x);
   const TileDesc td = gload(l.tiles, tile);
   const GraphDev gd = graph_of<kBatch>(l, tile);
@@ -341,12 +365,18 @@ __global__ __launch_bounds__(kBlock) void k_prep(LaunchArgs l, int32_t in_dtype,
   const gptr<typename Store<D>::T> x0 =
       to_global(static_cast<typename Store<D>::T *>(x0v)) + gd.row_off * C;
   const gptr<const int32_t> row_ptr = to_global(gd.row_ptr), col = to_global(gd.col);
+  const double *cen = l.centre ? l.centre +
+                                     (static_cast<int64_t>(graph_index<kBatch>(l, tile)) * groups +
+                                      grp) * C
+                               : nullptr;
   if (td.r0 < io.num_cells) {
     const int n = (td.r1 - td.r0) * C;
     for (int i = threadIdx.x; i < n; i += kBlock) {
       const int64_t r = td.r0 + i / C;
       const int c = i % C;
-      x0[r * C + c] = Store<D>::from_f64(load_in(io.x_in, in_dtype, r * io.ld_in + col0 + c));
+      double v = load_in(io.x_in, in_dtype, r * io.ld_in + col0 + c);
+      if (cen) v = v - to_global(cen)[c] * sqrt(to_global(gd.deg)[r] + sigma);
+      x0[r * C + c] = Store<D>::from_f64(v);
     }
     return;
   }
@@ -373,10 +403,85 @@ __global__ __launch_bounds__(kBlock) void k_prep(LaunchArgs l, int32_t in_dtype,
       for (int off = G >> 1; off > 0; off >>= 1) s[c] += __shfl_xor(s[c], off);
     if (live && lane == 0) {
       const double m = static_cast<double>(p1 - p0);
+      const double vr = cen ? sqrt(to_global(gd.deg)[r] + sigma) : 0.0;
 #pragma unroll
-      for (int c = 0; c < C; ++c)
-        x0[static_cast<int64_t>(r) * C + c] = Store<D>::from_f64(m > 0 ? s[c] / m : 0.0);
+      for (int c = 0; c < C; ++c) {
+        double v = m > 0 ? s[c] / m : 0.0;
+        if (cen) v = v - to_global(cen)[c] * vr;
+        x0[static_cast<int64_t>(r) * C + c] = Store<D>::from_f64(v);
+      }
     }
+  }
+}
+
+// The centring vectors.  With v = sqrt(d + sigma), A~_sigma v = v exactly
+// (Theorem 1 with the self-loop), so A~^k (x - c v) + c v = A~^k x for any c.
+// c = sum over cells of x / sum over cells of v (per graph, sigma group and
+// column) makes c v match x on average; 16-bit iterates of x - c v then lose
+// far less to rounding than iterates of x.
+struct GroupSigmas {
+  int32_t n;
+  double s[kMaxTerms];
+};
+
+// Per tile of the all-rows list: sums over its cell rows of x (C columns)
+// and of sqrt(d + sigma_g) (one per group), block tree of fixed shape;
+// star-row tiles write zeros.  part[tile][C + groups].
+template <int C, bool kBatch>
+__global__ __launch_bounds__(kBlock) void k_centre_part(LaunchArgs l, int32_t in_dtype,
+                                                        int32_t col0, GroupSigmas gs,
+                                                        double *part) {
+  __shared__ double red[kBlock];
+  const uint32_t tile = blockIdx.x;
+  const TileDesc td = gload(l.tiles, tile);
+  const GraphDev gd = graph_of<kBatch>(l, tile);
+  const int nv = C + gs.n;
+  const bool cells = td.r0 < gd.io.num_cells;
+  for (int k = 0; k < nv; ++k) {
+    double a = 0.0;
+    if (cells) {
+      for (int32_t r = td.r0 + threadIdx.x; r < td.r1; r += kBlock)
+        a += k < C ? load_in(gd.io.x_in, in_dtype, static_cast<int64_t>(r) * gd.io.ld_in + col0 + k)
+                   : sqrt(to_global(gd.deg)[r] + gs.s[k - C]);
+    }
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+      if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[static_cast<int64_t>(tile) * nv + k] = red[0];
+    __syncthreads();
+  }
+}
+
+// One block per graph: sums its tiles' partials (strided per thread, then a
+// block tree: a fixed order) and writes centre[graph][g][q] = sum x_q /
+// sum v_g (0 when the graph has no cells).
+template <int C, bool kBatch>
+__global__ __launch_bounds__(kBlock) void k_centre_final(LaunchArgs l, const double *part,
+                                                         int32_t groups, double *centre) {
+  __shared__ double red[kBlock];
+  __shared__ double tot[16 + kMaxTerms];
+  const GraphDev gd = kBatch ? gload(l.graphs, blockIdx.x) : l.one;
+  const int nv = C + groups;
+  for (int k = 0; k < nv; ++k) {
+    double a = 0.0;
+    for (int32_t t = gd.tile_lo + threadIdx.x; t < gd.tile_hi; t += kBlock)
+      a += part[static_cast<int64_t>(t) * nv + k];
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+      if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) tot[k] = red[0];
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < groups * C; i += kBlock) {
+    const int g = i / C, q = i % C;
+    const double sv = tot[C + g];
+    centre[(static_cast<int64_t>(blockIdx.x) * groups + g) * C + q] = sv > 0.0 ? tot[q] / sv : 0.0;
   }
 }
 
@@ -413,9 +518,28 @@ gift_status enqueue_chunk(const FilterPlan &pl, const ChunkBuffers &bf, int32_t 
   using T = typename Store<D>::T;
   T *x0 = static_cast<T *>(bf.x0), *ping = static_cast<T *>(bf.ping),
     *pong = static_cast<T *>(bf.pong);
-  if (pl.num_tiles > 0) {
-    k_prep<D, C, kBatch><<<static_cast<unsigned>(pl.num_tiles), kBlock, 0, st>>>(
-        launch_args(pl, pl.groups.front(), false), pl.in_dtype, col0, x0);
+  const int32_t G = static_cast<int32_t>(pl.groups.size());
+  auto args = [&](const PlanGroup &grp, bool fin) {
+    LaunchArgs l = launch_args(pl, grp, fin);
+    l.centre = pl.centre ? bf.centre : nullptr;
+    return l;
+  };
+  const unsigned prep_grid = static_cast<unsigned>(pl.num_tiles);
+  if (pl.centre && pl.num_tiles > 0) {
+    GroupSigmas gs{};
+    gs.n = G;
+    for (int32_t g = 0; g < G; ++g) gs.s[g] = pl.groups[g].sigma;
+    k_centre_part<C, kBatch><<<prep_grid, kBlock, 0, st>>>(args(pl.groups.front(), false),
+                                                         pl.in_dtype, col0, gs, bf.centre_part);
+    GIFT_TRY(check_launch("k_centre_part"));
+    k_centre_final<C, kBatch><<<static_cast<unsigned>(pl.num_graphs), kBlock, 0, st>>>(
+        args(pl.groups.front(), false), bf.centre_part, G, bf.centre);
+    GIFT_TRY(check_launch("k_centre_final"));
+  }
+  if (!pl.centre && pl.num_tiles > 0) {
+    // one x0 serves every sigma group
+    k_prep<D, C, kBatch><<<prep_grid, kBlock, 0, st>>>(args(pl.groups.front(), false),
+                                                       pl.in_dtype, col0, x0, 0, G, 0.0);
     GIFT_TRY(check_launch("k_prep"));
   }
   FinalArgs fa{};
@@ -423,13 +547,23 @@ gift_status enqueue_chunk(const FilterPlan &pl, const ChunkBuffers &bf, int32_t 
   fa.in_dtype = pl.in_dtype;
   fa.out_dtype = pl.out_dtype;
   fa.col0 = col0;
+  fa.num_groups = G;
   for (int32_t t = 0; t < pl.num_terms; ++t) {
     fa.src[t] = bf.saved[t];
     fa.alpha[t] = pl.terms[t].alpha;
+    fa.term_sigma[t] = pl.terms[t].sigma;
+    for (int32_t g = 0; g < G; ++g)
+      if (pl.groups[g].sigma == pl.terms[t].sigma) fa.term_group[t] = g;
   }
   const size_t ng = pl.groups.size();
   for (size_t gi = 0; gi < ng; ++gi) {
     const PlanGroup &grp = pl.groups[gi];
+    if (pl.centre && pl.num_tiles > 0) {
+      // x0 - c v of this group's sigma
+      k_prep<D, C, kBatch><<<prep_grid, kBlock, 0, st>>>(args(grp, false), pl.in_dtype, col0, x0,
+                                                         static_cast<int32_t>(gi), G, grp.sigma);
+      GIFT_TRY(check_launch("k_prep"));
+    }
     const T *cur = x0;
     for (int32_t k = 1; k <= grp.kmax; ++k) {
       const bool fin = gi + 1 == ng && k == grp.kmax;
@@ -442,7 +576,7 @@ gift_status enqueue_chunk(const FilterPlan &pl, const ChunkBuffers &bf, int32_t 
       }
       const int64_t tiles = fin ? pl.num_final_tiles : pl.num_tiles;
       if (tiles > 0) {
-        const LaunchArgs l = launch_args(pl, grp, fin);
+        const LaunchArgs l = args(grp, fin);
         const unsigned grid = static_cast<unsigned>(tiles);
         const void *x = cur;
         void *y = dst;
@@ -557,6 +691,15 @@ size_t carve_chunk_buffers(const FilterPlan &pl, int C, unsigned char *base, Chu
     for (int32_t u = 0; u < t && same < 0; ++u)
       if (pl.terms[u].sigma == tm.sigma && pl.terms[u].order == tm.order) same = u;
     bf->saved[t] = same >= 0 ? bf->saved[same] : slot();
+  }
+  bf->centre_part = nullptr;
+  bf->centre = nullptr;
+  if (pl.centre) {
+    const size_t G = pl.groups.size();
+    bf->centre_part = reinterpret_cast<double *>(b + off);
+    off += round_up(sizeof(double) * (C + G) * static_cast<size_t>(pl.num_tiles + 1));
+    bf->centre = reinterpret_cast<double *>(b + off);
+    off += round_up(sizeof(double) * G * C * static_cast<size_t>(pl.num_graphs));
   }
   return off;
 }
@@ -744,7 +887,7 @@ gift_status exact_chunk(const gift_graph *g, const FilterPlan &pl, double tol, i
   double *bb = dots, *rho[2] = {dots + C, dots + 2 * C}, *pq = dots + 3 * C;
   const unsigned nb = static_cast<unsigned>(std::min<int64_t>(kCgBlocks, (R + kBlock - 1) / kBlock));
   k_prep<D, C, false><<<static_cast<unsigned>(pl.num_tiles), kBlock, 0, st>>>(
-      launch_args(pl, pl.groups.front(), false), pl.in_dtype, col0, b);
+      launch_args(pl, pl.groups.front(), false), pl.in_dtype, col0, b, 0, 1, 0.0);
   GIFT_TRY(check_launch("k_prep"));
   k_cg_init<D, C><<<nb, kBlock, 0, st>>>(b, x, r, p, R, part);
   GIFT_TRY(check_launch("k_cg_init"));
@@ -882,7 +1025,10 @@ gift_status filter_impl(const gift_graph *g, const gift_term *terms, int32_t nt,
   pl.in_dtype = in_dt;
   pl.out_dtype = out_dt;
   pl.one = GraphDev{g->row_ptr, g->col, nullptr, nullptr, 0,
-                    GraphIO{x_in, ld_in, y_out, ld_out, fixed, g->num_cells}};
+                    GraphIO{x_in, ld_in, y_out, ld_out, fixed, g->num_cells}, g->deg, 0,
+                    static_cast<int32_t>(pl.num_tiles)};
+  pl.centre = centred_storage(g->storage);
+  pl.num_graphs = 1;
   if (fixed_buf) {
     // the profiler creates events on first use; this path creates nothing
     pl.profile = false;
@@ -969,7 +1115,8 @@ extern "C" gift_status gift_filter_exact(const gift_graph *g, double sigma, cons
   pl.in_dtype = in_dt;
   pl.out_dtype = out_dt;
   pl.one = GraphDev{g->row_ptr, g->col, nullptr, nullptr, 0,
-                    GraphIO{x_in, ld_in, y_out, ld_out, fixed, g->num_cells}};
+                    GraphIO{x_in, ld_in, y_out, ld_out, fixed, g->num_cells}, g->deg, 0,
+                    static_cast<int32_t>(pl.num_tiles)};
   int64_t its = 0;
   for (int32_t col0 = 0; col0 < num_cols;) {
     const int C = chunk_width(num_cols - col0);
