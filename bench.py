@@ -297,9 +297,10 @@ def bench_batched(gift, W, torch, storage, reps=10):
         "batched_frac": round(nbytes / (ms_batch * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "max_normwise_diff_vs_per_design": worst,
         "schedule": {"tile_class": info["tile_class"], "chunk_cols": info["chunk_cols"],
+                     "xcd_affine": info["xcd_affine"],
                      "tuned": info["tuned"], "tune_s": round(create_s, 3),
-                     "candidates": [(c["tile_class"], c["chunk_cols"], round(c["ms"], 4))
-                                    for c in info["candidates"]]},
+                     "candidates": [(c["tile_class"], c["chunk_cols"], c["xcd_affine"],
+                                     round(c["ms"], 4)) for c in info["candidates"]]},
     }
 
 

@@ -492,10 +492,13 @@ typedef struct {
   int64_t device_bytes; /* device memory held by the batch itself           */
   double tuned_ms;      /* replay time of the chosen schedule when timed     */
   int32_t num_candidates;
-  int32_t reserved;
+  int32_t xcd_affine;   /* 1: every graph's tiles run on one XCD (its L2 keeps the
+                           graph's signal rows); 0: chunks of consecutive tiles
+                           dealt round-robin to the XCDs                      */
   int32_t cand_tile_class[GIFT_BATCH_MAX_CANDIDATES];
   int32_t cand_chunk_cols[GIFT_BATCH_MAX_CANDIDATES];
   double cand_ms[GIFT_BATCH_MAX_CANDIDATES]; /* replay time of each candidate */
+  int32_t cand_xcd_affine[GIFT_BATCH_MAX_CANDIDATES];
 } gift_batch_info;
 
 /*
@@ -509,10 +512,16 @@ typedef struct {
  *   terms       as in gift_filter_placement (copied).
  *   num_cols    columns of every graph's signal (>= 1).
  *   in_dtype, out_dtype   F32 or F64.
- *   tune        0: default schedule (tile class 0, widest column chunk);
+ *   tune        0: default schedule (tile class 0, widest column chunk,
+ *               chunks of tiles dealt round-robin to the XCDs);
  *               1: time every candidate schedule on zero inputs unless a
  *               batch of the same shape class was tuned before in this
- *               process, and keep the fastest; 2: always time.
+ *               process, and keep the fastest; 2: always time; 3: the
+ *               default schedule with the XCD-affine tile layout (every
+ *               graph's tiles on one XCD).  Candidates: tile class 0 or 1,
+ *               the widest chunk or half of it, either layout.  Every
+ *               schedule computes each row with the same arithmetic as
+ *               filtering its graph alone with that tile class.
  *   stream      orders the batch's device memory and the tuning runs; the
  *               call synchronises it before returning.
  *

@@ -93,10 +93,11 @@ class BatchInfo(C.Structure):
         ("device_bytes", C.c_int64),
         ("tuned_ms", C.c_double),
         ("num_candidates", C.c_int32),
-        ("reserved", C.c_int32),
+        ("xcd_affine", C.c_int32),
         ("cand_tile_class", C.c_int32 * BATCH_MAX_CANDIDATES),
         ("cand_chunk_cols", C.c_int32 * BATCH_MAX_CANDIDATES),
         ("cand_ms", C.c_double * BATCH_MAX_CANDIDATES),
+        ("cand_xcd_affine", C.c_int32 * BATCH_MAX_CANDIDATES),
     ]
 
 

@@ -389,7 +389,8 @@ class Batch:
                if not k.startswith("cand_") and k != "reserved"}
         n = inf.num_candidates
         out["candidates"] = [{"tile_class": inf.cand_tile_class[i],
-                              "chunk_cols": inf.cand_chunk_cols[i], "ms": inf.cand_ms[i]}
+                              "chunk_cols": inf.cand_chunk_cols[i],
+                              "xcd_affine": inf.cand_xcd_affine[i], "ms": inf.cand_ms[i]}
                              for i in range(n)]
         return out
 

@@ -7,9 +7,11 @@
 // uploads the table with the caller's I/O pointers and launches the graph.
 //
 // Schedules differ in the tile class (entries per tile and the long-row
-// split) and in the column chunk width (one pass sequence per chunk: wide
+// split), in the column chunk width (one pass sequence per chunk: wide
 // chunks gather longer signal rows, narrow ones re-read the structure but
-// stage products in LDS).  The autotuner captures every candidate, times its
+// stage products in LDS) and in the tile layout: chunks of consecutive tiles
+// dealt round-robin to the XCDs, or every graph on one XCD so that the
+// signal rows its tiles gather stay in that XCD's L2.  The autotuner captures every candidate, times its
 // replays and keeps the fastest; the choice is cached per shape class.
 #include <algorithm>
 #include <cmath>
@@ -50,8 +52,21 @@ constexpr int kSlots = 4;  // pinned staging slots for the I/O table
 
 struct Candidate {
   int32_t tile_class;
-  int32_t chunk;  // widest column chunk
+  int32_t chunk;   // widest column chunk
+  int32_t affine;  // 1: XCD-affine tile layout, 0: chunks dealt round-robin
 };
+
+// out[p] = src[perm[p]] (and its graph) for perm[p] >= 0, else an empty tile
+// of graph `pad_graph` (rows [0, 0), entries [0, 0)).
+__global__ void k_permute_tiles(const int32_t *perm, int64_t n, const TileDesc *src,
+                                const int32_t *src_graph, int32_t pad_graph, TileDesc *out,
+                                int32_t *out_graph) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int32_t q = perm[p];
+  gstore(out, p, q >= 0 ? gload(src, q) : TileDesc{0, 0, 0, 0});
+  out_graph[p] = q >= 0 ? src_graph[q] : pad_graph;
+}
 
 // Column chunks of `num_cols` columns with chunks at most `widest` wide.
 std::vector<int> chunk_list(int num_cols, int widest) {
@@ -105,6 +120,15 @@ struct gift_batch {
   TileDesc *ftiles[kTileClasses] = {};
   int32_t *ftile_graph[kTileClasses] = {};
   int64_t num_ftiles[kTileClasses] = {};
+  // the same tiles laid out per XCD (XCD-affine schedule): every graph is
+  // given to one XCD and block b (on XCD b mod 8) takes tile b; short XCD
+  // lists are padded with empty tiles
+  TileDesc *atiles[kTileClasses] = {};
+  int32_t *atile_graph[kTileClasses] = {};
+  int64_t num_atiles[kTileClasses] = {};
+  TileDesc *aftiles[kTileClasses] = {};
+  int32_t *aftile_graph[kTileClasses] = {};
+  int64_t num_aftiles[kTileClasses] = {};
   // graph table [groups][graphs]
   std::vector<GraphDev> table;
   GraphDev *table_dev = nullptr;
@@ -138,6 +162,10 @@ void free_batch(gift_batch *b) {
     dev_free(b->tile_graph[c], b->home);
     dev_free(b->ftiles[c], b->home);
     dev_free(b->ftile_graph[c], b->home);
+    dev_free(b->atiles[c], b->home);
+    dev_free(b->atile_graph[c], b->home);
+    dev_free(b->aftiles[c], b->home);
+    dev_free(b->aftile_graph[c], b->home);
   }
   dev_free(b->table_dev, b->home);
   dev_free(b->buffers, b->home);
@@ -183,16 +211,99 @@ gift_status concat_tiles(gift_batch *b, int c, bool cells_only, TileDesc **out,
   return GIFT_OK;
 }
 
+// The XCD-affine layout of class c: every graph goes to one XCD (largest
+// graphs first, each to the XCD with the least work so far), so the signal
+// rows a graph's tiles gather stay in that XCD's L2 while they run.  List
+// position i * 8 + k holds the i-th tile of XCD k (block b runs on XCD
+// b mod 8); shorter XCD lists are padded with empty tiles.  Built for the
+// all-rows list and for the cell-rows list of the last pass.
+gift_status affine_lists(gift_batch *b, int c) {
+  const size_t ng = b->graphs.size();
+  std::vector<int64_t> wgt(ng);
+  std::vector<size_t> order(ng);
+  int32_t pad_graph = -1;
+  for (size_t g = 0; g < ng; ++g) {
+    wgt[g] = b->graphs[g]->nnz + b->graphs[g]->num_rows;
+    order[g] = g;
+    if (pad_graph < 0 && b->graphs[g]->num_rows > 0) pad_graph = static_cast<int32_t>(g);
+  }
+  if (pad_graph < 0) return GIFT_OK;  // no rows at all: no launches
+  std::stable_sort(order.begin(), order.end(),
+                   [&](size_t x, size_t y) { return wgt[x] > wgt[y]; });
+  std::vector<int64_t> load(kXcds, 0);
+  std::vector<uint32_t> xcd_of(ng, 0);
+  for (size_t g : order) {
+    uint32_t k = 0;
+    for (uint32_t j = 1; j < kXcds; ++j)
+      if (load[j] < load[k]) k = j;
+    xcd_of[g] = k;
+    load[k] += wgt[g];
+  }
+  for (int cells_only = 0; cells_only <= 1; ++cells_only) {
+    std::vector<std::vector<int32_t>> lists(kXcds);
+    int64_t off = 0;
+    for (size_t g = 0; g < ng; ++g) {
+      const int64_t n = cells_only ? b->graphs[g]->num_tiles_cells[c] : b->graphs[g]->num_tiles[c];
+      for (int64_t i = 0; i < n; ++i) lists[xcd_of[g]].push_back(static_cast<int32_t>(off + i));
+      off += n;
+    }
+    size_t longest = 0;
+    for (const auto &l : lists) longest = std::max(longest, l.size());
+    const int64_t nout = static_cast<int64_t>(longest) * kXcds;
+    if (nout >= (int64_t(1) << 31) - 1)
+      return set_error(GIFT_EUNSUPPORTED, "batch has too many tiles for the XCD-affine layout");
+    std::vector<int32_t> perm(static_cast<size_t>(nout), -1);
+    for (uint32_t k = 0; k < kXcds; ++k)
+      for (size_t i = 0; i < lists[k].size(); ++i) perm[i * kXcds + k] = lists[k][i];
+    TileDesc **out = cells_only ? &b->aftiles[c] : &b->atiles[c];
+    int32_t **out_graph = cells_only ? &b->aftile_graph[c] : &b->atile_graph[c];
+    GIFT_TRY(dev_alloc(reinterpret_cast<void **>(out), sizeof(TileDesc) * (nout + 1), b->home,
+                       "batch XCD-affine tiles"));
+    GIFT_TRY(dev_alloc(reinterpret_cast<void **>(out_graph), sizeof(int32_t) * (nout + 1),
+                       b->home, "batch XCD-affine tile graphs"));
+    (cells_only ? b->num_aftiles[c] : b->num_atiles[c]) = nout;
+    if (nout == 0) continue;
+    Scratch sc(b->home);
+    int32_t *dperm = nullptr;
+    GIFT_TRY(sc.get(&dperm, perm.size(), "tile permutation"));
+    GIFT_HIP(hipMemcpyAsync(dperm, perm.data(), sizeof(int32_t) * perm.size(),
+                            hipMemcpyHostToDevice, b->home));
+    k_permute_tiles<<<grid_for(nout), kBlock, 0, b->home>>>(
+        dperm, nout, cells_only ? b->ftiles[c] : b->tiles[c],
+        cells_only ? b->ftile_graph[c] : b->tile_graph[c], pad_graph, *out, *out_graph);
+    GIFT_TRY(check_launch("k_permute_tiles"));
+    // `perm` must outlive the copy
+    GIFT_HIP(hipStreamSynchronize(b->home));
+  }
+  return GIFT_OK;
+}
+
 void use_schedule(gift_batch *b, const Candidate &cand) {
   FilterPlan &pl = b->plan;
   const int c = cand.tile_class;
   pl.tile_class = c;
-  pl.tiles = b->tiles[c];
-  pl.tile_graph = b->tile_graph[c];
-  pl.num_tiles = b->num_tiles[c];
-  pl.final_tiles = b->ftiles[c];
-  pl.final_tile_graph = b->ftile_graph[c];
-  pl.num_final_tiles = b->num_ftiles[c];
+  pl.identity_map = cand.affine != 0;
+  if (cand.affine) {
+    pl.tiles = b->atiles[c];
+    pl.tile_graph = b->atile_graph[c];
+    pl.num_tiles = b->num_atiles[c];
+    pl.final_tiles = b->aftiles[c];
+    pl.final_tile_graph = b->aftile_graph[c];
+    pl.num_final_tiles = b->num_aftiles[c];
+    pl.centre_tiles = b->tiles[c];
+    pl.centre_tile_graph = b->tile_graph[c];
+    pl.num_centre_tiles = b->num_tiles[c];
+  } else {
+    pl.tiles = b->tiles[c];
+    pl.tile_graph = b->tile_graph[c];
+    pl.num_tiles = b->num_tiles[c];
+    pl.final_tiles = b->ftiles[c];
+    pl.final_tile_graph = b->ftile_graph[c];
+    pl.num_final_tiles = b->num_ftiles[c];
+    pl.centre_tiles = nullptr;
+    pl.centre_tile_graph = nullptr;
+    pl.num_centre_tiles = 0;
+  }
   b->chunks = chunk_list(b->num_cols, cand.chunk);
   // each graph's tiles in the all-rows list of this class (the table is
   // uploaded with the next run)
@@ -212,6 +323,7 @@ void use_schedule(gift_batch *b, const Candidate &cand) {
 // grow with the tile count, so size them for the class with the most tiles.
 size_t buffers_for(const gift_batch *b, int widest) {
   FilterPlan pl = b->plan;
+  pl.centre_tiles = nullptr;
   pl.num_tiles = std::max(b->num_tiles[0], b->num_tiles[1]);
   return chunk_buffer_bytes(pl, chunk_width(std::min(widest, b->num_cols)));
 }
@@ -308,8 +420,9 @@ gift_status alloc_buffers(gift_batch *b, size_t bytes) {
 gift_status autotune(gift_batch *b, Candidate *best) {
   std::vector<Candidate> cands;
   const int w0 = chunk_width(b->num_cols);
-  for (int c = 0; c < kTileClasses; ++c)
-    for (int w = w0; w >= 1 && w * 4 >= w0; w /= 2) cands.push_back(Candidate{c, w});
+  for (int a = 0; a <= 1; ++a)
+    for (int c = 0; c < kTileClasses; ++c)
+      for (int w = w0; w >= 1 && w * 2 >= w0; w /= 2) cands.push_back(Candidate{c, w, a});
   if (cands.size() > GIFT_BATCH_MAX_CANDIDATES) cands.resize(GIFT_BATCH_MAX_CANDIDATES);
 
   const size_t ng = b->graphs.size();
@@ -338,6 +451,7 @@ gift_status autotune(gift_batch *b, Candidate *best) {
     GIFT_TRY(time_replays(b, 3, &ms));
     b->info.cand_tile_class[i] = cands[i].tile_class;
     b->info.cand_chunk_cols[i] = cands[i].chunk;
+    b->info.cand_xcd_affine[i] = cands[i].affine;
     b->info.cand_ms[i] = ms;
     if (i == 0 || ms < best_ms) {
       best_ms = ms;
@@ -533,7 +647,7 @@ extern "C" gift_status gift_batch_create(const gift_graph *const *graphs, int32_
     return set_error(GIFT_EUNSUPPORTED, "in_dtype must be F32 or F64");
   if (out_dtype != GIFT_F32 && out_dtype != GIFT_F64)
     return set_error(GIFT_EUNSUPPORTED, "out_dtype must be F32 or F64");
-  if (tune < 0 || tune > 2) return set_error(GIFT_EINVAL, "tune %d not in [0, 2]", tune);
+  if (tune < 0 || tune > 3) return set_error(GIFT_EINVAL, "tune %d not in [0, 3]", tune);
   int dev = 0;
   GIFT_HIP(hipGetDevice(&dev));
   for (int32_t g = 0; g < num_graphs; ++g) {
@@ -615,6 +729,7 @@ extern "C" gift_status gift_batch_create(const gift_graph *const *graphs, int32_
     s = concat_tiles(b, c, false, &b->tiles[c], &b->tile_graph[c], &b->num_tiles[c]);
     if (s == GIFT_OK)
       s = concat_tiles(b, c, true, &b->ftiles[c], &b->ftile_graph[c], &b->num_ftiles[c]);
+    if (s == GIFT_OK) s = affine_lists(b, c);
     if (s != GIFT_OK) return fail(s);
   }
 
@@ -635,7 +750,7 @@ extern "C" gift_status gift_batch_create(const gift_graph *const *graphs, int32_
   pl.profile = false;
 
   // schedule: default, cached or tuned
-  Candidate best{0, chunk_width(num_cols)};
+  Candidate best{0, chunk_width(num_cols), tune == 3 ? 1 : 0};
   const TuneKey key{dev, b->storage, num_cols, num_terms, log2_bucket(b->nnz),
                     log2_bucket(b->R), log2_bucket(num_graphs)};
   b->info.tuned = 0;
@@ -670,13 +785,15 @@ extern "C" gift_status gift_batch_create(const gift_graph *const *graphs, int32_
   in.num_graphs = num_graphs;
   in.tile_class = best.tile_class;
   in.chunk_cols = best.chunk;
+  in.xcd_affine = best.affine;
   in.num_rows = b->R;
   in.nnz = b->nnz;
   in.num_tiles = b->num_tiles[best.tile_class];
   in.device_bytes = static_cast<int64_t>(b->buffer_bytes + sizeof(GraphDev) * b->table.size());
   for (int c = 0; c < kTileClasses; ++c)
-    in.device_bytes += static_cast<int64_t>((sizeof(TileDesc) + 4) *
-                                            (b->num_tiles[c] + b->num_ftiles[c] + 2));
+    in.device_bytes += static_cast<int64_t>(
+        (sizeof(TileDesc) + 4) *
+        (b->num_tiles[c] + b->num_ftiles[c] + b->num_atiles[c] + b->num_aftiles[c] + 4));
   *out = b;
   return GIFT_OK;
 }

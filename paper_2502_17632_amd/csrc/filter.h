@@ -70,6 +70,14 @@ struct FilterPlan {
   // column; the final combine adds c v_sigma back.
   bool centre = false;
   int64_t num_graphs = 1;
+  // Block b works on tile b itself (the tile lists are already laid out so
+  // that block b's XCD, b mod 8, owns the tile) instead of xcd_remap(b).
+  bool identity_map = false;
+  // With identity_map, the centring sums run over each graph's contiguous
+  // tiles in this all-rows list (tile_lo/tile_hi index it).
+  const TileDesc *centre_tiles = nullptr;
+  const int32_t *centre_tile_graph = nullptr;
+  int64_t num_centre_tiles = 0;
 };
 
 // Signal buffers of one column chunk: [R][C] storage-type rows.

@@ -59,7 +59,14 @@ struct LaunchArgs {
   GraphDev one;
   // centring multipliers [graphs][groups][C] (16-bit storage), else NULL
   double *centre;
+  // block b takes tile b (the list is laid out per XCD) rather than
+  // xcd_remap(b)
+  int32_t identity_map;
 };
+
+__device__ __forceinline__ uint32_t tile_of_block(const LaunchArgs &l) {
+  return l.identity_map ? blockIdx.x : xcd_remap(blockIdx.x, gridDim.x);
+}
 
 template <bool kBatch>
 __device__ __forceinline__ GraphDev graph_of(const LaunchArgs &l, uint32_t tile) {
@@ -104,24 +111,42 @@ __device__ __forceinline__ void emit_row(const FinalArgs &f, const GraphDev &gd,
     const GraphIO &io = gd.io;
     const bool fixed = io.fixed && to_global(io.fixed)[lr];
     const int64_t srow = gd.row_off + lr;
+    double s[C];
+    if (fixed) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) s[c] = load_in(io.x_in, f.in_dtype, lr * io.ld_in + f.col0 + c);
+    } else {
+#pragma unroll
+      for (int c = 0; c < C; ++c) s[c] = 0.0;
+      const double dl = cen ? to_global(gd.deg)[lr] : 0.0;
+      // every column sums the terms in term order
+      for (int t = 0; t < f.num_terms; ++t) {
+        const T *src = static_cast<const T *>(f.src[t]);
+        double v[C];
+        if (src) {
+          const auto row = load_row<T, C>(src, srow);
+#pragma unroll
+          for (int c = 0; c < C; ++c) v[c] = static_cast<double>(S::load(row.v[c]));
+        } else {
+#pragma unroll
+          for (int c = 0; c < C; ++c) v[c] = static_cast<double>(acc[c]);
+        }
+        if (cen) {
+          const double vt = sqrt(dl + f.term_sigma[t]);
+          const gptr<const double> ct = to_global(cen) + f.term_group[t] * C;
+#pragma unroll
+          for (int c = 0; c < C; ++c) v[c] = v[c] + ct[c] * vt;
+        }
+        const double a = f.alpha[t];
+#pragma unroll
+        for (int c = 0; c < C; ++c) s[c] = s[c] + a * v[c];
+      }
+    }
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      double s = 0.0;
-      if (fixed) {
-        s = load_in(io.x_in, f.in_dtype, lr * io.ld_in + f.col0 + c);
-      } else {
-        const double dl = cen ? to_global(gd.deg)[lr] : 0.0;
-        for (int t = 0; t < f.num_terms; ++t) {
-          const T *src = static_cast<const T *>(f.src[t]);
-          double v = src ? static_cast<double>(S::load(to_global(src)[srow * C + c]))
-                         : static_cast<double>(acc[c]);
-          if (cen) v = v + to_global(cen)[f.term_group[t] * C + c] * sqrt(dl + f.term_sigma[t]);
-          s = s + f.alpha[t] * v;
-        }
-      }
       const int64_t o = lr * io.ld_out + f.col0 + c;
-      if (f.out_dtype == GIFT_F64) to_global(static_cast<double *>(io.y_out))[o] = s;
-      else to_global(static_cast<float *>(io.y_out))[o] = static_cast<float>(s);
+      if (f.out_dtype == GIFT_F64) to_global(static_cast<double *>(io.y_out))[o] = s[c];
+      else to_global(static_cast<float *>(io.y_out))[o] = static_cast<float>(s[c]);
     }
   }
 }
@@ -160,7 +185,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm(LaunchArgs l, const void *xin, 
   __shared__ A lval[kStageProducts ? 1 : TCL::kCap];
   __shared__ A lred[kBlock / kWave][C];
 
-  const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t tile = tile_of_block(l);
   const int tid = threadIdx.x;
   const TileDesc td = gload(l.tiles, tile);
   const GraphDev gd = graph_of<kBatch>(l, tile);
@@ -311,17 +336,21 @@ __global__ __launch_bounds__(kBlock) void k_spmm(LaunchArgs l, const void *xin, 
           for (int c = 0; c < C; ++c) acc[c] += lprod[q * C + c];
         }
       } else {
+        // four gathers in flight per lane, then their products in order
         int q = loff[rr] + lane;
-        for (; q + G < q1; q += 2 * G) {
-          const auto xa = load_row<T, C>(x, lcol[q]);
-          const auto xb = load_row<T, C>(x, lcol[q + G]);
-          const A va = lval[q], vb = lval[q + G];
+        for (; q + 3 * G < q1; q += 4 * G) {
+          typename SigRow<T, C>::V xr[4];
+          A vr[4];
 #pragma unroll
-          for (int c = 0; c < C; ++c) acc[c] += va * S::load(xa.v[c]);
+          for (int u = 0; u < 4; ++u) xr[u] = load_row<T, C>(x, lcol[q + u * G]);
 #pragma unroll
-          for (int c = 0; c < C; ++c) acc[c] += vb * S::load(xb.v[c]);
+          for (int u = 0; u < 4; ++u) vr[u] = lval[q + u * G];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int c = 0; c < C; ++c) acc[c] += vr[u] * S::load(xr[u].v[c]);
         }
-        if (q < q1) {
+        for (; q < q1; q += G) {
           const auto xa = load_row<T, C>(x, lcol[q]);
           const A va = lval[q];
 #pragma unroll
@@ -358,7 +387,7 @@ template <int D, int C, bool kBatch>
 __global__ __launch_bounds__(kBlock) void k_prep(LaunchArgs l, int32_t in_dtype, int32_t col0,
                                                  void *x0v, int32_t grp, int32_t groups,
                                                  double sigma) {
-  const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t tile = tile_of_block(l);
   const TileDesc td = gload(l.tiles, tile);
   const GraphDev gd = graph_of<kBatch>(l, tile);
   const GraphIO &io = gd.io;
@@ -425,33 +454,59 @@ struct GroupSigmas {
 };
 
 // Per tile of the all-rows list: sums over its cell rows of x (C columns)
-// and of sqrt(d + sigma_g) (one per group), block tree of fixed shape;
-// star-row tiles write zeros.  part[tile][C + groups].
+// and of sqrt(d + sigma_g) (one per group); star-row tiles write zeros.
+// One pass over the rows (each thread a fixed set of rows, accumulated in
+// order), then per value a wave reduction by a fixed shuffle pattern and the
+// waves' results added in wave order.  part[tile][C + groups].
 template <int C, bool kBatch>
 __global__ __launch_bounds__(kBlock) void k_centre_part(LaunchArgs l, int32_t in_dtype,
                                                         int32_t col0, GroupSigmas gs,
                                                         double *part) {
-  __shared__ double red[kBlock];
+  constexpr int kGroupsInRegs = 4;
+  __shared__ double wsum[kBlock / kWave][16 + kMaxTerms];
   const uint32_t tile = blockIdx.x;
   const TileDesc td = gload(l.tiles, tile);
   const GraphDev gd = graph_of<kBatch>(l, tile);
   const int nv = C + gs.n;
   const bool cells = td.r0 < gd.io.num_cells;
-  for (int k = 0; k < nv; ++k) {
-    double a = 0.0;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  double ax[C], av[kGroupsInRegs];
+#pragma unroll
+  for (int k = 0; k < C; ++k) ax[k] = 0.0;
+#pragma unroll
+  for (int g = 0; g < kGroupsInRegs; ++g) av[g] = 0.0;
+  for (int g0 = 0; g0 < (gs.n > 0 ? gs.n : 1); g0 += kGroupsInRegs) {
     if (cells) {
-      for (int32_t r = td.r0 + threadIdx.x; r < td.r1; r += kBlock)
-        a += k < C ? load_in(gd.io.x_in, in_dtype, static_cast<int64_t>(r) * gd.io.ld_in + col0 + k)
-                   : sqrt(to_global(gd.deg)[r] + gs.s[k - C]);
+      for (int32_t r = td.r0 + threadIdx.x; r < td.r1; r += kBlock) {
+        if (g0 == 0) {
+#pragma unroll
+          for (int k = 0; k < C; ++k)
+            ax[k] += load_in(gd.io.x_in, in_dtype, static_cast<int64_t>(r) * gd.io.ld_in + col0 + k);
+        }
+        const double d = to_global(gd.deg)[r];
+#pragma unroll
+        for (int g = 0; g < kGroupsInRegs; ++g)
+          if (g0 + g < gs.n) av[g] += sqrt(d + gs.s[g0 + g]);
+      }
     }
-    red[threadIdx.x] = a;
-    __syncthreads();
-    for (int off = kBlock / 2; off > 0; off >>= 1) {
-      if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-      __syncthreads();
+    // reduce this round's values: x columns (first round) and its groups
+#pragma unroll
+    for (int k = 0; k < C + kGroupsInRegs; ++k) {
+      const bool isx = k < C;
+      if (!isx && g0 + (k - C) >= gs.n) continue;
+      if (isx && g0 != 0) continue;
+      double v = isx ? ax[k] : av[k - C];
+      for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+      if (lane == 0) wsum[wave][isx ? k : C + g0 + (k - C)] = v;
     }
-    if (threadIdx.x == 0) part[static_cast<int64_t>(tile) * nv + k] = red[0];
-    __syncthreads();
+#pragma unroll
+    for (int g = 0; g < kGroupsInRegs; ++g) av[g] = 0.0;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < nv; k += kBlock) {
+    double t = 0.0;
+    for (int w = 0; w < kBlock / kWave; ++w) t += wsum[w][k];
+    part[static_cast<int64_t>(tile) * nv + k] = t;
   }
 }
 
@@ -509,6 +564,7 @@ LaunchArgs launch_args(const FilterPlan &pl, const PlanGroup &grp, bool fin) {
   l.one = pl.one;
   l.one.val = grp.val;
   l.one.diag = grp.diag;
+  l.identity_map = pl.identity_map ? 1 : 0;
   return l;
 }
 
@@ -529,11 +585,19 @@ gift_status enqueue_chunk(const FilterPlan &pl, const ChunkBuffers &bf, int32_t 
     GroupSigmas gs{};
     gs.n = G;
     for (int32_t g = 0; g < G; ++g) gs.s[g] = pl.groups[g].sigma;
-    k_centre_part<C, kBatch><<<prep_grid, kBlock, 0, st>>>(args(pl.groups.front(), false),
-                                                         pl.in_dtype, col0, gs, bf.centre_part);
+    // the sums run over every graph's contiguous tiles
+    LaunchArgs lc = args(pl.groups.front(), false);
+    int64_t nct = pl.num_tiles;
+    if (pl.centre_tiles) {
+      lc.tiles = pl.centre_tiles;
+      lc.tile_graph = pl.centre_tile_graph;
+      nct = pl.num_centre_tiles;
+    }
+    k_centre_part<C, kBatch><<<static_cast<unsigned>(nct), kBlock, 0, st>>>(
+        lc, pl.in_dtype, col0, gs, bf.centre_part);
     GIFT_TRY(check_launch("k_centre_part"));
     k_centre_final<C, kBatch><<<static_cast<unsigned>(pl.num_graphs), kBlock, 0, st>>>(
-        args(pl.groups.front(), false), bf.centre_part, G, bf.centre);
+        lc, bf.centre_part, G, bf.centre);
     GIFT_TRY(check_launch("k_centre_final"));
   }
   if (!pl.centre && pl.num_tiles > 0) {
@@ -696,8 +760,9 @@ size_t carve_chunk_buffers(const FilterPlan &pl, int C, unsigned char *base, Chu
   bf->centre = nullptr;
   if (pl.centre) {
     const size_t G = pl.groups.size();
+    const int64_t ct = pl.centre_tiles ? pl.num_centre_tiles : pl.num_tiles;
     bf->centre_part = reinterpret_cast<double *>(b + off);
-    off += round_up(sizeof(double) * (C + G) * static_cast<size_t>(pl.num_tiles + 1));
+    off += round_up(sizeof(double) * (C + G) * static_cast<size_t>(ct + 1));
     bf->centre = reinterpret_cast<double *>(b + off);
     off += round_up(sizeof(double) * G * C * static_cast<size_t>(pl.num_graphs));
   }

@@ -147,7 +147,7 @@ def test_batch_arguments_rejected_without_device_work():
     assert lib.gift_batch_create(graphs, 1, terms, 1, 0, 0, 0, 1, None, C.byref(out)) == L.GIFT_EINVAL
     assert lib.gift_batch_create(graphs, 1, terms, 1, 2, 2, 0, 1, None,
                                  C.byref(out)) == L.GIFT_EUNSUPPORTED
-    assert lib.gift_batch_create(graphs, 1, terms, 1, 2, 0, 0, 3, None, C.byref(out)) == L.GIFT_EINVAL
+    assert lib.gift_batch_create(graphs, 1, terms, 1, 2, 0, 0, 4, None, C.byref(out)) == L.GIFT_EINVAL
     assert lib.gift_batch_create(graphs, 1, terms, 1, 2, 0, 0, 1, None, None) == L.GIFT_EINVAL
     assert out.value is None
     io = (L.BatchIO * 1)()

@@ -45,18 +45,21 @@ def to_dev(x, dtype):
     return torch.tensor(np.asarray(x, dtype=np.float64), dtype=dtype, device="cuda")
 
 
-@pytest.mark.parametrize("storage", ["f32", "bf16"])
-def test_batch_default_schedule_is_bit_identical_to_alone(designs, storage):
+@pytest.mark.parametrize("storage,tune", [("f32", 0), ("bf16", 0), ("f32", 3), ("bf16", 3)])
+def test_batch_default_schedule_is_bit_identical_to_alone(designs, storage, tune):
+    """The default schedule, with the round-robin and with the XCD-affine
+    tile layout: every design's result equals filtering it alone."""
     import torch
     import paper_2502_17632_amd as gift
     nls, xs = designs
     graphs = build_all(nls, storage, [4.0])
     xt = [to_dev(x, torch.float32) for x in xs]
-    b = gift.Batch(graphs, *EQ4, num_cols=8, tune=0)
+    b = gift.Batch(graphs, *EQ4, num_cols=8, tune=tune)
     info = b.info()
-    log(f"[batch] default schedule {storage}: {info['num_graphs']} graphs, "
-        f"rows {info['num_rows']}, tiles {info['num_tiles']}")
+    log(f"[batch] default schedule {storage}, xcd_affine {info['xcd_affine']}: "
+        f"{info['num_graphs']} graphs, rows {info['num_rows']}, tiles {info['num_tiles']}")
     assert info["tuned"] == 0 and info["tile_class"] == 0 and info["chunk_cols"] == 8
+    assert info["xcd_affine"] == (1 if tune == 3 else 0)
     ys = b.run(xt)
     alone = [gift.filter_placement(g, *EQ4, x) for g, x in zip(graphs, xt)]
     torch.cuda.synchronize()
