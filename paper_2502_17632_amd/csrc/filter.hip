@@ -398,14 +398,35 @@ __global__ __launch_bounds__(kBlock) void k_prep(LaunchArgs l, int32_t in_dtype,
                                      (static_cast<int64_t>(graph_index<kBatch>(l, tile)) * groups +
                                       grp) * C
                                : nullptr;
+  using V = typename SigRow<typename Store<D>::T, C>::V;
   if (td.r0 < io.num_cells) {
-    const int n = (td.r1 - td.r0) * C;
-    for (int i = threadIdx.x; i < n; i += kBlock) {
-      const int64_t r = td.r0 + i / C;
-      const int c = i % C;
-      double v = load_in(io.x_in, in_dtype, r * io.ld_in + col0 + c);
-      if (cen) v = v - to_global(cen)[c] * sqrt(to_global(gd.deg)[r] + sigma);
-      x0[r * C + c] = Store<D>::from_f64(v);
+    // a thread per row: all of its loads first (two rows at a time), one
+    // square root per row, the row stored with one vector store
+    for (int32_t r = td.r0 + threadIdx.x; r < td.r1; r += 2 * kBlock) {
+      const int32_t r2 = r + kBlock;
+      const bool two = r2 < td.r1;
+      double v[2][C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        v[0][c] = load_in(io.x_in, in_dtype, static_cast<int64_t>(r) * io.ld_in + col0 + c);
+        v[1][c] = two ? load_in(io.x_in, in_dtype, static_cast<int64_t>(r2) * io.ld_in + col0 + c)
+                      : 0.0;
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (h == 1 && !two) break;
+        const int32_t rr = h ? r2 : r;
+        V out;
+        const double vr = cen ? sqrt(to_global(gd.deg)[rr] + sigma) : 0.0;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          double e = v[h][c];
+          if (cen) e = e - to_global(cen)[c] * vr;
+          out.v[c] = Store<D>::from_f64(e);
+        }
+        gstore(reinterpret_cast<V *>(static_cast<typename Store<D>::T *>(x0v) + gd.row_off * C),
+               rr, out);
+      }
     }
     return;
   }
@@ -422,7 +443,23 @@ __global__ __launch_bounds__(kBlock) void k_prep(LaunchArgs l, int32_t in_dtype,
     double s[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) s[c] = 0.0;
-    for (int32_t q = p0 + lane; q < p1; q += G) {
+    // four cells per lane at a time: their columns, then their rows
+    int32_t q = p0 + lane;
+    for (; q + 3 * G < p1; q += 4 * G) {
+      int64_t j[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) j[u] = col[q + u * G];
+      double xv[4][C];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int c = 0; c < C; ++c) xv[u][c] = load_in(io.x_in, in_dtype, j[u] * io.ld_in + col0 + c);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int c = 0; c < C; ++c) s[c] += xv[u][c];
+    }
+    for (; q < p1; q += G) {
       const int64_t j = col[q];
 #pragma unroll
       for (int c = 0; c < C; ++c) s[c] += load_in(io.x_in, in_dtype, j * io.ld_in + col0 + c);
