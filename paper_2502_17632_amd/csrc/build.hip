@@ -14,12 +14,14 @@
 //      pins per tile, long nets alone)
 //   1. per net tile, in LDS: distinct cells of every net, ascending (rank of
 //      each pin among the net's first occurrences); long nets by a block-wide
-//      bitonic sort in LDS or a merge sort through global memory
+//      bitonic sort in LDS or a merge sort through global memory.  The same
+//      kernel counts the directed entries of every cell row: one atomic add
+//      per distinct (net, cell), whose old value is the slice of that cell's
+//      entries from this net within the row (arbitrary order of the slices;
+//      the atomics overlap the LDS work of the net tiles)
 //   2. per net: clique or star, virtual id, weight
-//   3. per cell row: number of directed entries (atomic histogram over pins;
-//      the atomic's old value is the pin's slice within the row), exclusive
-//      scan -> row slices; emit each pin's (col, net) keys into its slice
-//      (arbitrary order of the slices within a row)
+//   3. exclusive scan of the row counts -> row slices; emit each pin's
+//      (col, net) keys into its slice
 //   4. per row tile, in LDS: sort each row's keys by (col, net) (rank among
 //      the row's keys, which are distinct), count distinct columns.  The
 //      sorted order fixes every summation order below, so the result does
@@ -140,7 +142,25 @@ struct NetArgs {
   uint32_t *flag;
   uint32_t *tmp32;   // scratch of the global merge sort [P]
   const TileDesc *tiles;  // nets [r0, r1), pins [p0, p1) of every tile
+  int64_t T;         // star threshold (0: no stars)
+  int32_t *cnt;      // entries per cell row (zeroed before the launch)
+  int32_t *slot;     // per distinct-cell slot: its slice start within the row
 };
+
+// Entries a net of m distinct cells adds to each of its cells' rows: m - 1
+// for a clique, 1 (the virtual node) for a star, none for m < 2.
+__device__ __forceinline__ int32_t row_entries(int64_t m, int64_t T) {
+  if (m < 2) return 0;
+  return (T > 0 && m > T) ? 1 : static_cast<int32_t>(m - 1);
+}
+
+// Reserves the slice of cell c's entries from a net of m distinct cells in
+// row c; q is the cell's slot in ucell.  Cells outside [0, N) were flagged
+// and get no slice (the build fails on the flag).
+__device__ __forceinline__ void reserve_slice(const NetArgs &a, int64_t q, int32_t c, int64_t m) {
+  const int32_t k = row_entries(m, a.T);
+  if (k > 0 && c >= 0 && c < a.N) a.slot[q] = atomicAdd(&a.cnt[c], k);
+}
 
 // Writes the distinct values of the sorted keys src[0..n) to out[0..) and
 // returns their count.  Force-inlined at call sites whose `src` is known to be
@@ -209,6 +229,10 @@ __device__ __forceinline__ void net_long(const NetArgs &a, int64_t e, int64_t lo
     a.M[e] = static_cast<int32_t>(m);
     if (bad_s) atomicOr(a.flag, kFlagBadPin);
   }
+  // the distinct cells this block just wrote (visible to it after the
+  // barrier)
+  __syncthreads();
+  for (int64_t i = threadIdx.x; i < m; i += kBlock) reserve_slice(a, lo + i, a.ucell[lo + i], m);
 }
 
 constexpr int kNetSmem = 10 * 1024;
@@ -218,6 +242,7 @@ static_assert(kNetSortCap * 4 <= kNetSmem && kChunk32 * 4 <= kNetSmem, "long net
 
 __global__ __launch_bounds__(kBlock) void k_net_tiles(NetArgs a) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[kNetSmem];
+  __shared__ int32_t mloc[kBTileRows];
   __shared__ int bad_s;
   const TileDesc td = a.tiles[blockIdx.x];
   const int64_t e0 = td.r0, e1 = td.r1, q0 = td.p0, q1 = td.p1;
@@ -278,6 +303,13 @@ __global__ __launch_bounds__(kBlock) void k_net_tiles(NetArgs a) {
     first[i] = f ? 1 : 0;
   }
   __syncthreads();
+  for (int k = threadIdx.x; k < ns; k += kBlock) {
+    int m = 0;
+    for (int i = loff[k]; i < loff[k + 1]; ++i) m += first[i];
+    a.M[e0 + k] = m;
+    mloc[k] = m;
+  }
+  __syncthreads();
   for (int i = threadIdx.x; i < n; i += kBlock) {
     if (!first[i]) continue;
     const int k = seg[i];
@@ -289,12 +321,9 @@ __global__ __launch_bounds__(kBlock) void k_net_tiles(NetArgs a) {
       ur += ((first[j] != 0) & (key[j] < me)) + ((first[j + 1] != 0) & (key[j + 1] < me)) +
             ((first[j + 2] != 0) & (key[j + 2] < me)) + ((first[j + 3] != 0) & (key[j + 3] < me));
     for (; j < end; ++j) ur += (first[j] && key[j] < me) ? 1 : 0;
-    a.ucell[q0 + loff[k] + ur] = static_cast<int32_t>(me);
-  }
-  for (int k = threadIdx.x; k < ns; k += kBlock) {
-    int m = 0;
-    for (int i = loff[k]; i < loff[k + 1]; ++i) m += first[i];
-    a.M[e0 + k] = m;
+    const int64_t q = q0 + loff[k] + ur;
+    a.ucell[q] = static_cast<int32_t>(me);
+    reserve_slice(a, q, static_cast<int32_t>(me), mloc[k]);
   }
   if (threadIdx.x == 0 && bad_s) atomicOr(a.flag, kFlagBadPin);
 }
@@ -368,24 +397,7 @@ struct EmitArgs {
   KeyLayout L;
 };
 
-// Counts the entries of every cell row and reserves each pin's slice in its
-// row at the same time: the atomic returns the slice's start within the row
-// (arbitrary order among the row's pins; the row sort makes the result
-// independent of it).
-__global__ void k_count(EmitArgs a, int32_t *cnt, int32_t *slot) {
-  int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (p >= a.P) return;
-  int64_t e = a.pin_net[p];
-  if (e < 0 || e >= a.E) return;
-  int64_t i = p - a.net_ptr[e];
-  int64_t m = a.M[e];
-  if (m < 2 || i < 0 || i >= m) return;
-  int32_t c = a.ucell[p];
-  if (c < 0 || c >= a.N) return;
-  slot[p] = atomicAdd(&cnt[c], a.is_star[e] ? 1 : static_cast<int32_t>(m - 1));
-}
-
-// Writes each pin's (col, net) keys into the slice k_count reserved.  The
+// Writes each pin's (col, net) keys into the slice k_net_tiles reserved.  The
 // block's 256 pins first publish their slices in LDS (start, length, net,
 // position in the net); then the block's threads take the keys one each,
 // in slice order, so consecutive threads write consecutive addresses of a
@@ -722,12 +734,13 @@ __global__ __launch_bounds__(kBlock) void k_row_merge_tiles(MergeArgs a) {
       double s = key_weight(key[i], a);
       for (int j = i + 1; j < end && key_col(key[j], a.L) == c; ++j) s = s + key_weight(key[j], a);
       a.col[o0 + pos] = static_cast<int32_t>(c);
-      a.w[o0 + pos] = s;
       mw[pos] = s;
       ++pos;
     }
   }
   __syncthreads();
+  // the weights (two thirds of the bytes written) leave LDS coalesced
+  for (int i = threadIdx.x; i < total; i += kBlock) a.w[o0 + i] = mw[i];
   for (int k = threadIdx.x; k < ns; k += kBlock) {
     double d = 0.0;
     for (int i = moff[k]; i < moff[k + 1]; ++i) d = d + mw[i];
@@ -989,13 +1002,19 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
   GIFT_TRY(sc.get(&pin_net, P, "pin nets"));
   GIFT_TRY(sc.get(&tmp32, P, "net sort scratch"));
 
-  // 1. distinct cells per net (tile descriptors first: one load per block
-  //    instead of two dependent ones; pin offsets fit int32 by the check above)
+  // 1. distinct cells per net and the row counts (tile descriptors first:
+  //    one load per block instead of two dependent ones; pin offsets fit
+  //    int32 by the check above)
+  int32_t *cnt = nullptr, *slot = nullptr;
+  GIFT_TRY(sc.get(&cnt, N, "row counts"));
+  GIFT_TRY(sc.get(&slot, P, "pin slices"));
+  GIFT_HIP(hipMemsetAsync(cnt, 0, N * 4 + 4, st));
   TileDesc *net_descs = nullptr;
   GIFT_TRY(sc.get(&net_descs, num_net_tiles + 1, "net tile descriptors"));
   GIFT_TRY(tile_descs(net_tiles, net_ptr, num_net_tiles, st, net_descs));
   if (num_net_tiles > 0) {
-    NetArgs na{net_ptr, pin, E, P, N, M, ucell, pin_net, flag, tmp32, net_descs};
+    NetArgs na{net_ptr, pin,   E,         P,   N,   M,   ucell, pin_net,
+               flag,    tmp32, net_descs, d->star_threshold, cnt, slot};
     k_net_tiles<<<static_cast<unsigned>(num_net_tiles), kBlock, 0, st>>>(na);
     GIFT_TRY(check_launch("k_net_tiles"));
   }
@@ -1022,18 +1041,13 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
   k_virtual_map<<<grid_for(E), kBlock, 0, st>>>(is_star, vscan, E, virt_net);
   GIFT_TRY(check_launch("k_virtual_map"));
 
-  // 3. entries per cell row, row tiles over the pre-merge slices
-  int32_t *cnt = nullptr, *row_tiles = nullptr, *slot = nullptr;
+  // 3. row tiles over the pre-merge slices
+  int32_t *row_tiles = nullptr;
   int64_t *zoff = nullptr, *row_tile_counts = nullptr;
-  GIFT_TRY(sc.get(&cnt, N, "row counts"));
-  GIFT_TRY(sc.get(&slot, P, "pin slices"));
   GIFT_TRY(sc.get(&zoff, N + 1, "row offsets"));
   GIFT_TRY(sc.get(&row_tiles, N + 2, "row tiles"));
   GIFT_TRY(sc.get(&row_tile_counts, 2, "row tile counts"));
-  GIFT_HIP(hipMemsetAsync(cnt, 0, N * 4 + 4, st));
   EmitArgs ea{net_ptr, ucell, pin_net, M, is_star, vscan, E, P, N, KeyLayout{}};
-  k_count<<<grid_for(P), kBlock, 0, st>>>(ea, cnt, slot);
-  GIFT_TRY(check_launch("k_count"));
   GIFT_TRY(scan_i32_to_i64(cnt, zoff, N, st));
   GIFT_TRY(build_tiles64(zoff, N, N, kBuildTiles, st, row_tiles, row_tile_counts));
 
