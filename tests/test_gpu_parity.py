@@ -58,6 +58,32 @@ def test_medium(medium, medium_oracle, storage):
     assert_close(y, ref, storage, f"medium {storage}")
 
 
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
+def test_centred_16bit_on_the_fixed_point(storage):
+    """Theorem 1 with the self-loop: v = sqrt(d + sigma) satisfies
+    A~_sigma v = v, so with one sigma the filter of x = k v is (sum of alpha)
+    k v.  The 16-bit path iterates on x - c v with c = sum x / sum v; for
+    x = k v that iterate is only the input's rounding residue, so the result
+    must match the float64 oracle far inside the 16-bit gate (1e-5 against
+    2e-2).  A centring on another vector, with another c, or without c v
+    added back in the combine misses by orders of magnitude."""
+    # nets of at most 16 cells: no star rows, whose start value (the mean of
+    # their cells) is not k v
+    nl = W.make_netlist(50_000, 500, 55_000, cap=16, seed=7, name="capped")
+    og = O.build_graph(nl.num_cells, nl.net_ptr, nl.pin_cell, star_threshold=16)
+    assert og.num_virtual == 0
+    v = np.sqrt(og.deg + 4.0)
+    x = np.stack([3.5 * v, 120.0 * v], axis=1)
+    y, ref, g, og = run_pair(nl, x, EQ4, storage=storage, star_threshold=16, og=og,
+                             label=f"fixed point {storage}")
+    xin = x.astype(np.float32).astype(np.float64)
+    # the premise, on the oracle: the signal is (up to its float32 rounding)
+    # the fixed point, and the equal weights sum to 1
+    assert np.abs(ref - xin).max() <= 1e-6 * np.abs(xin).max()
+    err = assert_close(y, ref, storage, f"fixed point {storage}")
+    assert np.all(err <= 1e-5), err
+
+
 def test_medium_two_over_m_paper_terms(medium):
     x = W.make_signal(medium, seed=3)
     y, ref, g, og = run_pair(medium, x, PAPER, storage="f32", star_threshold=16,
