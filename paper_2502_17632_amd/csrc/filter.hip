@@ -570,10 +570,14 @@ __global__ __launch_bounds__(kBlock) void k_centre_final(LaunchArgs l, const dou
     if (threadIdx.x == 0) tot[k] = red[0];
     __syncthreads();
   }
+  // a column whose sum is not finite (a NaN or infinite input) is not
+  // centred, so the bad value reaches only the rows the filter carries it
+  // to, as without centring
   for (int i = threadIdx.x; i < groups * C; i += kBlock) {
     const int g = i / C, q = i % C;
     const double sv = tot[C + g];
-    centre[(static_cast<int64_t>(blockIdx.x) * groups + g) * C + q] = sv > 0.0 ? tot[q] / sv : 0.0;
+    const double c = sv > 0.0 ? tot[q] / sv : 0.0;
+    centre[(static_cast<int64_t>(blockIdx.x) * groups + g) * C + q] = isfinite(c) ? c : 0.0;
   }
 }
 

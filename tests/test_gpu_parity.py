@@ -84,6 +84,32 @@ def test_centred_16bit_on_the_fixed_point(storage):
     assert np.all(err <= 1e-5), err
 
 
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
+def test_centred_16bit_keeps_bad_inputs_local(storage):
+    """A NaN or infinite input reaches, in one pass, only its own row and its
+    neighbours' rows.  Centring must not spread it through the centring
+    multiplier to every row: the non-finite pattern of the 16-bit result
+    equals the float32 one."""
+    import torch
+    import paper_2502_17632_amd as gift
+    nl = W.tiny(seed=2)
+    x = W.make_signal(nl, seed=2).astype(np.float32)
+    x[17, 0] = np.nan
+    x[99, 1] = np.inf
+    xt = torch.tensor(x, device="cuda")
+    finite = {}
+    for st in ("f32", storage):
+        g = gift.build_graph(nl.num_cells, nl.net_ptr, nl.pin_cell, storage=st, sigmas=[4.0])
+        y = gift.filter_placement(g, [4.0], [1], [1.0], xt)
+        torch.cuda.synchronize()
+        finite[st] = np.isfinite(y.cpu().numpy())
+        g.close()
+    log(f"[parity] bad inputs {storage}: {int((~finite[storage]).sum())} non-finite outputs "
+        f"(f32: {int((~finite['f32']).sum())})")
+    assert (~finite["f32"]).sum() < 0.05 * finite["f32"].size
+    assert np.array_equal(finite["f32"], finite[storage])
+
+
 def test_medium_two_over_m_paper_terms(medium):
     x = W.make_signal(medium, seed=3)
     y, ref, g, og = run_pair(medium, x, PAPER, storage="f32", star_threshold=16,
