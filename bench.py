@@ -189,10 +189,11 @@ def build_roofline(torch, nl, build_ms, b_bytes, copy_gbs):
                    "attainable copy bandwidth"}
 
 
-def filter_leg(gift, W, torch, nl, storage, terms, cols_x, label, reps=20):
+def filter_leg(gift, W, torch, nl, storage, terms, cols_x, label, reps=20, also_class1=False):
     """Filter-only timing on a resident graph: whole filter (events) and the
     SpMM pass (library profiler), with algorithmic bytes and roofline
-    fraction."""
+    fraction; with also_class1, the same under SpMM tile class 1 (smaller
+    tiles, more blocks), which small graphs fill the GPU better with."""
     g = gift.build_graph(nl.num_cells, nl.net_ptr, nl.pin_cell, star_threshold=STAR,
                          storage=storage, sigmas=sorted(set(terms[0])))
     info = g.info()
@@ -224,6 +225,24 @@ def filter_leg(gift, W, torch, nl, storage, terms, cols_x, label, reps=20):
            "spmm_pass_frac": round(pass_bytes / (pass_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
            if pass_us else None}
     yh = y.double().cpu().numpy()
+    if also_class1:
+        g.set_tile_class(1)
+        ms1 = timed_events(torch, lambda: gift.filter_placement(g, *terms, x, fixed=fx, out=y,
+                                                                out_dtype=dt), reps)
+        gift.profile_enable(True)
+        timed_events(torch, lambda: gift.filter_placement(g, *terms, x, fixed=fx, out=y,
+                                                          out_dtype=dt), 5, warm=0)
+        sp1 = gift.profile_collect("spmm")
+        gift.profile_enable(False)
+        us1 = sp1["total_ms"] / max(sp1["launches"], 1) * 1e3
+        b1 = sp1["bytes"] / max(sp1["launches"], 1)
+        out["tile_class1"] = {"filter_ms": round(ms1, 4), "nnz_cols_per_s": work / (ms1 * 1e-3),
+                              "spmm_pass_us": round(us1, 2),
+                              "spmm_pass_frac": round(b1 / (us1 * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
+                              if us1 else None,
+                              "note": "gift_graph_set_tile_class(1); the default (class 0) "
+                                      "keeps single-graph results bit-identical to the batch "
+                                      "default schedule and the server"}
     g.close()
     return out, yh
 
@@ -745,7 +764,8 @@ def main():
         out["medium_f32"], _ = filter_leg(
             gift, W, torch, nm, "f32", EQ4, W.make_signal(nm).astype(np.float32),
             "medium: 200k+2k cells, 220k nets, Zipf(2.2) pins <= 1000, 90% local; star above "
-            "16 cells; sigma 4, orders 1,2,4,8, equal weights; 2 columns, float32")
+            "16 cells; sigma 4, orders 1,2,4,8, equal weights; 2 columns, float32",
+            also_class1=True)
         out["medium_f32"]["note"] = ("fits in the 256 MB MALL, so its GB/s may exceed what "
                                      "HBM alone delivers")
         out["batched"] = [bench_batched(gift, W, torch, st) for st in ("f32", "bf16")]
