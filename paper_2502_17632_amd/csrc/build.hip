@@ -944,6 +944,30 @@ gift_status read_scalars(hipStream_t st, const int64_t *const *ptrs, int n, int6
 
 namespace {
 
+// A pooled side stream held for the rest of a build.  On an early return its
+// queued work may still use the build's scratch, so the stream is drained
+// before it goes back to the pool (and before the scratch, declared earlier,
+// is released).
+struct SideGuard {
+  SideStream s{};
+  bool idle = false;  // set once the build knows the stream has no work left
+  ~SideGuard() {
+    if (!s.stream) return;
+    if (!idle) (void)hipStreamSynchronize(s.stream);
+    side_stream_release(s);
+  }
+};
+
+// Makes `side` wait for everything enqueued on `st` so far.
+gift_status fork_to(hipStream_t st, const SideStream &side) {
+  if (hipEventRecord(side.ready, st) != hipSuccess ||
+      hipStreamWaitEvent(side.stream, side.ready, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return set_error(GIFT_EDEVICE, "side stream ordering failed");
+  }
+  return GIFT_OK;
+}
+
 gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) {
   const int64_t N = d->num_cells, E = d->num_nets;
   Scratch sc(st);
@@ -1019,6 +1043,21 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
     GIFT_TRY(check_launch("k_net_tiles"));
   }
 
+  // 2-3. two independent chains: the net classes here, the row offsets and
+  //      row tiles on a side stream, joined before the sizes are read back
+  SideGuard side;
+  GIFT_TRY(side_stream_acquire(&side.s));
+  int32_t *row_tiles = nullptr;
+  int64_t *zoff = nullptr, *row_tile_counts = nullptr;
+  GIFT_TRY(sc.get(&zoff, N + 1, "row offsets"));
+  GIFT_TRY(sc.get(&row_tiles, N + 2, "row tiles"));
+  GIFT_TRY(sc.get(&row_tile_counts, 2, "row tile counts"));
+  // (these blocks and cnt were allocated on this stream before the fork, so
+  // the event orders the side stream after their earlier users)
+  GIFT_TRY(fork_to(st, side.s));
+  GIFT_TRY(scan_i32_to_i64(cnt, zoff, N, side.s.stream));
+  GIFT_TRY(build_tiles64(zoff, N, N, kBuildTiles, side.s.stream, row_tiles, row_tile_counts));
+
   // 2. classify
   int32_t *is_star = nullptr, *virt_net = nullptr;
   int64_t *star_code = nullptr, *vscan = nullptr;
@@ -1041,15 +1080,13 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
   k_virtual_map<<<grid_for(E), kBlock, 0, st>>>(is_star, vscan, E, virt_net);
   GIFT_TRY(check_launch("k_virtual_map"));
 
-  // 3. row tiles over the pre-merge slices
-  int32_t *row_tiles = nullptr;
-  int64_t *zoff = nullptr, *row_tile_counts = nullptr;
-  GIFT_TRY(sc.get(&zoff, N + 1, "row offsets"));
-  GIFT_TRY(sc.get(&row_tiles, N + 2, "row tiles"));
-  GIFT_TRY(sc.get(&row_tile_counts, 2, "row tile counts"));
+  // join: this stream waits for the row offsets and row tiles
+  if (hipEventRecord(side.s.done, side.s.stream) != hipSuccess ||
+      hipStreamWaitEvent(st, side.s.done, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return set_error(GIFT_EDEVICE, "side stream ordering failed");
+  }
   EmitArgs ea{net_ptr, ucell, pin_net, M, is_star, vscan, E, P, N, KeyLayout{}};
-  GIFT_TRY(scan_i32_to_i64(cnt, zoff, N, st));
-  GIFT_TRY(build_tiles64(zoff, N, N, kBuildTiles, st, row_tiles, row_tile_counts));
 
   // sizes back to the host: flag, {V, star entries}, Z, row tiles, largest
   // net
@@ -1115,25 +1152,18 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
   int64_t *tile_counts = nullptr;
   GIFT_TRY(sc.get(&tile_counts, 2 * kTileClasses, "tile counts"));
   for (int c = 0; c < kTileClasses; ++c) GIFT_TRY(sc.get(&tstart[c], R + 2, "tile starts"));
-  SideStream side{};
-  GIFT_TRY(side_stream_acquire(&side));
-  gift_status ss = GIFT_OK;
   // everything the side stream reads or writes was allocated above, so it
   // is ordered after all earlier users of those blocks by this event
-  if (hipEventRecord(side.ready, st) != hipSuccess ||
-      hipStreamWaitEvent(side.stream, side.ready, 0) != hipSuccess) {
-    (void)hipGetLastError();
-    ss = set_error(GIFT_EDEVICE, "side stream ordering failed");
-  }
+  gift_status ss = fork_to(st, side.s);
   // 6. merge the cell rows here; the star rows (a disjoint part of the CSR)
   //    on the side stream
   if (ss == GIFT_OK && V > 0) {
-    k_star_rows<<<grid_for(V * kWave), kBlock, 0, side.stream>>>(
+    k_star_rows<<<grid_for(V * kWave), kBlock, 0, side.s.stream>>>(
         virt_net, net_ptr, M, ucell, wnet, g->row_ptr, N, V, g->col, g->w, g->deg);
     ss = check_launch("k_star_rows");
   }
   for (int c = 0; c < kTileClasses && ss == GIFT_OK; ++c)
-    ss = build_tiles64(rp64, R, N, kSpmmTiles[c], side.stream, tstart[c], tile_counts + 2 * c);
+    ss = build_tiles64(rp64, R, N, kSpmmTiles[c], side.s.stream, tstart[c], tile_counts + 2 * c);
   if (ss == GIFT_OK && num_row_tiles > 0) {
     MergeArgs ma{zoff, zsort, wnet, g->row_ptr, row_descs, g->col, g->w, g->deg,
                  L, N, d->weight_model};
@@ -1148,13 +1178,12 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
     ptrs[0] = rp64 + R;
     ptrs[1] = rp64 + N;
     for (int i = 0; i < 2 * kTileClasses; ++i) ptrs[2 + i] = tile_counts + i;
-    ss = read_scalars(side.stream, ptrs, 2 + 2 * kTileClasses, h2);
+    ss = read_scalars(side.s.stream, ptrs, 2 + 2 * kTileClasses, h2);
   }
-  // the side stream is idle here unless a call above failed: then wait for
-  // it before its scratch and the stream go back to their pools
-  if (ss != GIFT_OK) (void)hipStreamSynchronize(side.stream);
-  side_stream_release(side);
+  // the side stream is idle once its readback returned; otherwise the guard
+  // drains it
   GIFT_TRY(ss);
+  side.idle = true;
   g->nnz = h2[0];
   g->nnz_cells = h2[1];
   // the side stream's work is complete (its readback returned), so this
