@@ -251,6 +251,30 @@ def pin_star_schur(lib):
         gc.close(); gs.close()
 
 
+def pin_star_start_value(lib):
+    """The start value of a star's virtual row (reading D4: the mean of its
+    cells), by a closed form of eq. A_formulation.  One star net of M cells
+    and weight g = M w(M): every cell has degree g and the virtual node M g,
+    so one pass gives, for cell c,
+        y_c = g / sqrt((g + s)(M g + s)) * x_v + s / (g + s) * x_c,
+    with x_v the virtual row's start value; a start other than the mean of
+    the cells (another divisor, a missing cell) changes every y_c."""
+    for m, model, s, x in ((5, O.W_INV_M1, 2.0, [3.0, -1.0, 7.5, 0.25, 10.0]),
+                           (7, O.W_TWO_OVER_M, 0.5, [1.0, 2.0, 4.0, 8.0, 16.0, 32.0, 64.0])):
+        net_ptr = np.array([0, m], dtype=np.int64)
+        pins = np.arange(m, dtype=np.int32)[::-1].copy()
+        g = O.build_graph(m, net_ptr, pins, weight_model=model, star_threshold=m - 1, lib=lib)
+        assert g.num_virtual == 1
+        w = 1.0 / (m - 1) if model == O.W_INV_M1 else 2.0 / m
+        gam = m * w
+        xv = sum(x) / m
+        a_cv = gam / np.sqrt((gam + s) * (m * gam + s))
+        exp = np.array([a_cv * xv + s / (gam + s) * xc for xc in x])
+        y = g.filter(np.array(x)[:, None], [s], [1], [1.0])[:, 0]
+        assert np.allclose(y, exp, rtol=1e-14, atol=1e-14), (y, exp)
+        g.close()
+
+
 def pin_generated_invariants(lib):
     """On a generated clique-model netlist: weights are symmetric bit for bit,
     with w = 1/(M-1) every cell's degree is the number of nets it is on, and
@@ -604,7 +628,7 @@ def pin_import_csr(lib):
 
 ALL_PINS = [pin_golden_two_cell, pin_clique_closed_form, pin_hand_built,
             pin_brute_force_structure, pin_spectral, pin_theorem1_fixed_point,
-            pin_spectrum, pin_isolated_and_fixed, pin_star_schur,
+            pin_spectrum, pin_isolated_and_fixed, pin_star_schur, pin_star_start_value,
             pin_generated_invariants, pin_invalid_input, pin_evaluate_hand,
             pin_evaluate_dense, pin_exact_filter, pin_bin_density, pin_import_csr]
 
