@@ -268,6 +268,23 @@ def bench_tiny_latency(gift, W, torch):
         lat.append((time.perf_counter() - t0) * 1e3)
     dev_ms = timed_events(torch, lambda: gift.filter_placement(g, *EQ4, x, fixed=fx, out=y,
                                                                out_dtype=torch.float64), 50)
+    # the same filter captured once into a HIP graph (a batch of this one
+    # design, default schedule) and replayed: the launch overhead goes away
+    b = gift.Batch([g], *EQ4, num_cols=2, in_dtype=torch.float64, out_dtype=torch.float64,
+                   tune=0)
+    y2 = torch.empty_like(x)
+    for _ in range(3):
+        b.run([x], [y2], fixed=[fx])
+    torch.cuda.synchronize()
+    lat2 = []
+    for _ in range(50):
+        t0 = time.perf_counter()
+        b.run([x], [y2], fixed=[fx])
+        torch.cuda.synchronize()
+        lat2.append((time.perf_counter() - t0) * 1e3)
+    dev2_ms = timed_events(torch, lambda: b.run([x], [y2], fixed=[fx]), 50)
+    same = bool(torch.equal(y, y2))
+    b.close()
     g.close()
     import numpy as np
     return {"workload": "tiny: 2,000 + 200 cells, 2,500 nets, 2 + Geom(0.5) pins <= 8, uniform; "
@@ -276,7 +293,13 @@ def bench_tiny_latency(gift, W, torch):
             "filter_latency_ms_p50": round(float(np.percentile(lat, 50)), 4),
             "filter_latency_ms_p99": round(float(np.percentile(lat, 99)), 4),
             "filter_device_ms": round(dev_ms, 4),
-            "note": "latency = call to completion on the host (launch-bound); device = events"}
+            "captured_latency_ms_p50": round(float(np.percentile(lat2, 50)), 4),
+            "captured_latency_ms_p99": round(float(np.percentile(lat2, 99)), 4),
+            "captured_device_ms": round(dev2_ms, 4),
+            "captured_equal_to_uncaptured": same,
+            "note": "latency = call to completion on the host (launch-bound); device = events; "
+                    "captured = the filter recorded once into a HIP graph (gift_batch_* with "
+                    "this one design) and replayed"}
 
 
 def bench_batched(gift, W, torch, storage, reps=10):
