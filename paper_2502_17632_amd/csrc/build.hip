@@ -334,7 +334,8 @@ __global__ __launch_bounds__(kBlock) void k_net_tiles(NetArgs a) {
 // Per net: star or clique, weight, the star code (star ? 1 | M << 32 : 0;
 // its exclusive scan gives every star net its virtual row and the number of
 // star entries before it); and the largest net size of the block into
-// bmax[blockIdx.x].
+// bmax[blockIdx.x] (one atomic max per block on a single word would
+// serialise thousands of blocks at the memory side).
 __global__ __launch_bounds__(kBlock) void k_classify(const int32_t *M, int64_t E, int64_t T,
                                                      int model, int32_t *is_star, double *wnet,
                                                      int64_t *star_code, int32_t *bmax) {
@@ -550,31 +551,31 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_tiles(RowArgs a) {
   __syncthreads();
   fill_segment_ids(loff, ns, seg);
   __syncthreads();
-  // rank of each key in its row (keys of a row are distinct); the key is the
-  // first of its column when no smaller key of the row has the same column
-  // (four keys per step, so four LDS reads are in flight per wait)
+  // rank of each key in its row (keys of a row are distinct).  The keys of
+  // the same column that sort before me lie in [first_of_col, me), so the
+  // key heads its column exactly when as many keys sort below first_of_col
+  // as below me (four keys per step, so four LDS reads are in flight per
+  // wait)
   for (int i = threadIdx.x; i < n; i += kBlock) {
     const int k = seg[i];
     const uint64_t me = key[i];
-    // keys of the same column that sort before me lie in [first_of_col, me)
     const uint64_t col_lo = (me >> a.L.col_shift) << a.L.col_shift;
-    int rank = 0;
-    bool h = true;
+    int rank = 0, below = 0;
     int j = loff[k];
     const int end = loff[k + 1];
     for (; j + 4 <= end; j += 4) {
       const uint64_t o0 = key[j], o1 = key[j + 1], o2 = key[j + 2], o3 = key[j + 3];
       rank += (o0 < me ? 1 : 0) + (o1 < me ? 1 : 0) + (o2 < me ? 1 : 0) + (o3 < me ? 1 : 0);
-      h = h & !(o0 >= col_lo & o0 < me) & !(o1 >= col_lo & o1 < me) &
-          !(o2 >= col_lo & o2 < me) & !(o3 >= col_lo & o3 < me);
+      below += (o0 < col_lo ? 1 : 0) + (o1 < col_lo ? 1 : 0) + (o2 < col_lo ? 1 : 0) +
+               (o3 < col_lo ? 1 : 0);
     }
     for (; j < end; ++j) {
       const uint64_t o = key[j];
       rank += o < me ? 1 : 0;
-      h = h & !(o >= col_lo & o < me);
+      below += o < col_lo ? 1 : 0;
     }
     a.zsort[z0 + loff[k] + rank] = me;
-    head[i] = h ? 1 : 0;
+    head[i] = rank == below ? 1 : 0;
   }
   __syncthreads();
   for (int k = threadIdx.x; k < ns; k += kBlock) {
@@ -991,11 +992,16 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
     return set_error(GIFT_EUNSUPPORTED, "netlist too large (cells+nets %lld)",
                      (long long)(N + E));
 
-  // error flags: the low word of a zeroed 64-bit word (read back as int64)
-  int64_t *flag64 = nullptr;
-  GIFT_TRY(sc.get(&flag64, 1, "flag"));
-  GIFT_HIP(hipMemsetAsync(flag64, 0, 8, st));
+  // one zeroed block: the error flags (the low word of a 64-bit word, read
+  // back as int64), the largest net size and the row counts (N + 1 int32)
+  int64_t *zero_blk = nullptr;
+  const int64_t zero_words = 2 + (N + 2) / 2;
+  GIFT_TRY(sc.get(&zero_blk, zero_words, "flags, largest net, row counts"));
+  GIFT_HIP(hipMemsetAsync(zero_blk, 0, zero_words * 8, st));
+  int64_t *flag64 = zero_blk;
   uint32_t *flag = reinterpret_cast<uint32_t *>(flag64);
+  int64_t *mmax = zero_blk + 1;
+  int32_t *cnt = reinterpret_cast<int32_t *>(zero_blk + 2);
 
   // 0. check net_ptr and tile the nets, then read the flag, the pin count
   //    and the tile count back together; nothing reads pins before the check
@@ -1029,10 +1035,8 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
   // 1. distinct cells per net and the row counts (tile descriptors first:
   //    one load per block instead of two dependent ones; pin offsets fit
   //    int32 by the check above)
-  int32_t *cnt = nullptr, *slot = nullptr;
-  GIFT_TRY(sc.get(&cnt, N, "row counts"));
+  int32_t *slot = nullptr;
   GIFT_TRY(sc.get(&slot, P, "pin slices"));
-  GIFT_HIP(hipMemsetAsync(cnt, 0, N * 4 + 4, st));
   TileDesc *net_descs = nullptr;
   GIFT_TRY(sc.get(&net_descs, num_net_tiles + 1, "net tile descriptors"));
   GIFT_TRY(tile_descs(net_tiles, net_ptr, num_net_tiles, st, net_descs));
@@ -1067,9 +1071,7 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
   GIFT_TRY(sc.get(&vscan, E + 1, "virtual ranks and star entry offsets"));
   GIFT_TRY(sc.get(&wnet, E, "net weights"));
   GIFT_TRY(sc.get(&virt_net, E, "virtual nets"));
-  int64_t *mmax = nullptr;
   int32_t *bmax = nullptr;
-  GIFT_TRY(sc.get(&mmax, 1, "largest net"));
   GIFT_TRY(sc.get(&bmax, grid_for(E), "largest net per block"));
   k_classify<<<grid_for(E), kBlock, 0, st>>>(M, E, d->star_threshold, d->weight_model, is_star,
                                              wnet, star_code, bmax);
