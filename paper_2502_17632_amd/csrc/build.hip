@@ -636,8 +636,8 @@ __device__ __forceinline__ double run_weight(const uint64_t *k, int64_t i, int64
   return s;
 }
 
-constexpr int kMergeSmem = 23 * 1024;
-static_assert((kBTileCap + 1) * 16 + 2 * (kBTileRows + 2) * 4 + (kBTileCap + 1) * 2 <= kMergeSmem,
+constexpr int kMergeSmem = 14 * 1024;
+static_assert((kBTileCap + 1) * 8 + 2 * (kBTileRows + 2) * 4 + (kBTileCap + 1) * 2 <= kMergeSmem,
               "row merge LDS");
 
 __global__ __launch_bounds__(kBlock) void k_row_merge_tiles(MergeArgs a) {
@@ -682,8 +682,9 @@ __global__ __launch_bounds__(kBlock) void k_row_merge_tiles(MergeArgs a) {
   }
   const int n = static_cast<int>(n64);
   uint64_t *key = reinterpret_cast<uint64_t *>(smem);
-  double *mw = reinterpret_cast<double *>(key + kBTileCap + 1);
-  int32_t *loff = reinterpret_cast<int32_t *>(mw + kBTileCap + 1);
+  // the merged weights replace the keys once every thread has read them
+  double *mw = reinterpret_cast<double *>(key);
+  int32_t *loff = reinterpret_cast<int32_t *>(key + kBTileCap + 1);
   int32_t *moff = loff + kBTileRows + 2;
   uint16_t *seg = reinterpret_cast<uint16_t *>(moff + kBTileRows + 2);
   {
@@ -727,18 +728,33 @@ __global__ __launch_bounds__(kBlock) void k_row_merge_tiles(MergeArgs a) {
     mine += (i == loff[seg[i]] || key_col(key[i], a.L) != key_col(key[i - 1], a.L)) ? 1 : 0;
   int32_t total;
   int32_t pos = block_excl_scan<int32_t>(mine, &total, tmp);
-  for (int i = b; i < b + kPer && i < n; ++i) {
-    const int k = seg[i];
-    const int end = loff[k + 1];
-    if (i == loff[k] || key_col(key[i], a.L) != key_col(key[i - 1], a.L)) {
-      const uint32_t c = key_col(key[i], a.L);
-      double s = key_weight(key[i], a);
-      for (int j = i + 1; j < end && key_col(key[j], a.L) == c; ++j) s = s + key_weight(key[j], a);
-      a.col[o0 + pos] = static_cast<int32_t>(c);
-      mw[pos] = s;
-      ++pos;
+  // each head's merged weight waits in a register until every thread is
+  // done reading keys
+  double hw[kPer];
+  int32_t hp[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int i = b + u;
+    hp[u] = -1;
+    if (i < n) {
+      const int k = seg[i];
+      const int end = loff[k + 1];
+      if (i == loff[k] || key_col(key[i], a.L) != key_col(key[i - 1], a.L)) {
+        const uint32_t c = key_col(key[i], a.L);
+        double s = key_weight(key[i], a);
+        for (int j = i + 1; j < end && key_col(key[j], a.L) == c; ++j)
+          s = s + key_weight(key[j], a);
+        a.col[o0 + pos] = static_cast<int32_t>(c);
+        hw[u] = s;
+        hp[u] = pos;
+        ++pos;
+      }
     }
   }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < kPer; ++u)
+    if (hp[u] >= 0) mw[hp[u]] = hw[u];
   __syncthreads();
   // the weights (two thirds of the bytes written) leave LDS coalesced
   for (int i = threadIdx.x; i < total; i += kBlock) a.w[o0 + i] = mw[i];
@@ -1164,8 +1180,10 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
         virt_net, net_ptr, M, ucell, wnet, g->row_ptr, N, V, g->col, g->w, g->deg);
     ss = check_launch("k_star_rows");
   }
-  for (int c = 0; c < kTileClasses && ss == GIFT_OK; ++c)
-    ss = build_tiles64(rp64, R, N, kSpmmTiles[c], side.s.stream, tstart[c], tile_counts + 2 * c);
+  static_assert(kTileClasses == 2, "both SpMM tile classes are built in one pass");
+  if (ss == GIFT_OK)
+    ss = build_tiles64_pair(rp64, R, N, kSpmmTiles[0], kSpmmTiles[1], side.s.stream, tstart[0],
+                            tstart[1], tile_counts, tile_counts + 2);
   if (ss == GIFT_OK && num_row_tiles > 0) {
     MergeArgs ma{zoff, zsort, wnet, g->row_ptr, row_descs, g->col, g->w, g->deg,
                  L, N, d->weight_model};

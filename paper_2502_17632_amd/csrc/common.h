@@ -231,6 +231,11 @@ gift_status tile_descs(const int32_t *tile_row, const int64_t *rp64, int64_t T, 
 // counts_dev[1] = tiles that start before row `split`.
 gift_status build_tiles64(const int64_t *off, int64_t R, int64_t split, TileShape sh,
                           hipStream_t st, int32_t *tile_row, int64_t *counts_dev);
+// The tiles of two shapes over the same offsets in one pass (one flag
+// kernel, one scan, one scatter); the results equal two build_tiles64 calls.
+gift_status build_tiles64_pair(const int64_t *off, int64_t R, int64_t split, TileShape s0,
+                               TileShape s1, hipStream_t st, int32_t *tile_row0,
+                               int32_t *tile_row1, int64_t *counts0, int64_t *counts1);
 
 // ---------------------------------------------------------------------------
 // Storage types.  bf16 and f16 are stored as raw 16-bit patterns; values are

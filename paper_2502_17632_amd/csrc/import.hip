@@ -77,10 +77,10 @@ gift_status import_impl(const gift_csr_desc *d, hipStream_t st, gift_graph *g) {
                                                     flag);
   GIFT_TRY(check_launch("k_import_rows"));
   int32_t *tstart[kTileClasses];
-  for (int c = 0; c < kTileClasses; ++c) {
-    GIFT_TRY(sc.get(&tstart[c], R + 2, "tile starts"));
-    GIFT_TRY(build_tiles64(rp64, R, R, kSpmmTiles[c], st, tstart[c], tile_counts + 2 * c));
-  }
+  for (int c = 0; c < kTileClasses; ++c) GIFT_TRY(sc.get(&tstart[c], R + 2, "tile starts"));
+  static_assert(kTileClasses == 2, "both SpMM tile classes are built in one pass");
+  GIFT_TRY(build_tiles64_pair(rp64, R, R, kSpmmTiles[0], kSpmmTiles[1], st, tstart[0], tstart[1],
+                              tile_counts, tile_counts + 2));
   int64_t h[1 + 2 * kTileClasses] = {};
   const int64_t *ptrs[1 + 2 * kTileClasses];
   ptrs[0] = reinterpret_cast<const int64_t *>(flag);

@@ -62,6 +62,49 @@ gift_status build_tiles_impl(const Off *off, int64_t R, int64_t split, TileShape
   return check_launch("k_tile_scatter");
 }
 
+// Both SpMM tile classes in one pass: per row the two start flags packed in
+// one 64-bit word (class 0 in the low half, class 1 in the high half), so
+// one 64-bit scan numbers the starts of both (the low half's total is at
+// most R < 2^31 and never carries into the high half).
+template <typename Off>
+__global__ void k_tile_flags2(const Off *off, int64_t R, int64_t split, TileShape s0,
+                              TileShape s1, int64_t *flag) {
+  int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  int64_t f = 1 | (int64_t(1) << 32);
+  if (r > 0 && r != split) {
+    const int64_t a = off[r - 1], b = off[r], c = off[r + 1];
+    const int64_t f0 = (a / s0.entries != b / s0.entries) || ((r - 1) / s0.rows != r / s0.rows) ||
+                       b - a > s0.long_row || c - b > s0.long_row;
+    const int64_t f1 = (a / s1.entries != b / s1.entries) || ((r - 1) / s1.rows != r / s1.rows) ||
+                       b - a > s1.long_row || c - b > s1.long_row;
+    f = f0 | (f1 << 32);
+  }
+  flag[r] = f;
+}
+
+__global__ void k_tile_scatter2(const int64_t *flag, const int64_t *pos, int64_t R, int64_t split,
+                                int32_t *tile_row0, int32_t *tile_row1, int64_t *counts0,
+                                int64_t *counts1) {
+  int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r < R) {
+    const int64_t f = flag[r], p = pos[r];
+    if (f & 0xffffffff) tile_row0[p & 0xffffffff] = static_cast<int32_t>(r);
+    if (f >> 32) tile_row1[p >> 32] = static_cast<int32_t>(r);
+  }
+  if (r == 0) {
+    const int64_t T = pos[R];
+    const int64_t T0 = T & 0xffffffff, T1 = T >> 32;
+    const int64_t S = split < R ? pos[split] : T;
+    tile_row0[T0] = static_cast<int32_t>(R);
+    tile_row1[T1] = static_cast<int32_t>(R);
+    counts0[0] = T0;
+    counts0[1] = S & 0xffffffff;  // tiles before the split row
+    counts1[0] = T1;
+    counts1[1] = S >> 32;
+  }
+}
+
 __global__ void k_tile_descs(const int32_t *tile_row, const int64_t *rp64, int64_t T,
                              TileDesc *out) {
   int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -82,6 +125,21 @@ gift_status tile_descs(const int32_t *tile_row, const int64_t *rp64, int64_t T, 
 gift_status build_tiles64(const int64_t *off, int64_t R, int64_t split, TileShape sh,
                           hipStream_t st, int32_t *tile_row, int64_t *counts_dev) {
   return build_tiles_impl<int64_t>(off, R, split, sh, st, tile_row, counts_dev);
+}
+
+gift_status build_tiles64_pair(const int64_t *off, int64_t R, int64_t split, TileShape s0,
+                               TileShape s1, hipStream_t st, int32_t *tile_row0,
+                               int32_t *tile_row1, int64_t *counts0, int64_t *counts1) {
+  Scratch sc(st);
+  int64_t *flag = nullptr, *pos = nullptr;
+  GIFT_TRY(sc.get(&flag, R, "tile flags"));
+  GIFT_TRY(sc.get(&pos, R + 1, "tile positions"));
+  k_tile_flags2<int64_t><<<grid_for(R), kBlock, 0, st>>>(off, R, split, s0, s1, flag);
+  GIFT_TRY(check_launch("k_tile_flags2"));
+  GIFT_TRY(scan_i64(flag, pos, R, st));
+  k_tile_scatter2<<<grid_for(R > 0 ? R : 1), kBlock, 0, st>>>(flag, pos, R, split, tile_row0,
+                                                              tile_row1, counts0, counts1);
+  return check_launch("k_tile_scatter2");
 }
 
 }  // namespace gift
