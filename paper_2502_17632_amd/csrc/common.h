@@ -228,9 +228,12 @@ constexpr TileShape kSpmmTiles[kTileClasses] = {
 gift_status tile_descs(const int32_t *tile_row, const int64_t *rp64, int64_t T, hipStream_t st,
                        TileDesc *out);
 // tile_row must hold R + 1 entries; counts_dev[0] = number of tiles T,
-// counts_dev[1] = tiles that start before row `split`.
+// counts_dev[1] = tiles that start before row `split`.  With `narrow`, the
+// same pass copies off[0..R] to 32 bits (read it only once off[R] < 2^31
+// is known).
 gift_status build_tiles64(const int64_t *off, int64_t R, int64_t split, TileShape sh,
-                          hipStream_t st, int32_t *tile_row, int64_t *counts_dev);
+                          hipStream_t st, int32_t *tile_row, int64_t *counts_dev,
+                          int32_t *narrow = nullptr);
 // The tiles of two shapes over the same offsets in one pass (one flag
 // kernel, one scan, one scatter); the results equal two build_tiles64 calls.
 gift_status build_tiles64_pair(const int64_t *off, int64_t R, int64_t split, TileShape s0,

@@ -19,10 +19,13 @@
 namespace gift {
 namespace {
 
+// narrow (optional): off[0..R] copied to 32 bits (the caller has checked
+// that off[R] < 2^31 before it reads the copy).
 template <typename Off>
 __global__ void k_tile_flags(const Off *off, int64_t R, int64_t split, TileShape sh,
-                             int32_t *flag) {
+                             int32_t *flag, int32_t *narrow) {
   int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (narrow && r <= R) narrow[r] = static_cast<int32_t>(off[r]);
   if (r >= R) return;
   int f = 1;
   if (r > 0 && r != split) {
@@ -48,13 +51,14 @@ __global__ void k_tile_scatter(const int32_t *flag, const int64_t *pos, int64_t 
 
 template <typename Off>
 gift_status build_tiles_impl(const Off *off, int64_t R, int64_t split, TileShape sh,
-                             hipStream_t st, int32_t *tile_row, int64_t *counts_dev) {
+                             hipStream_t st, int32_t *tile_row, int64_t *counts_dev,
+                             int32_t *narrow) {
   Scratch sc(st);
   int32_t *flag = nullptr;
   int64_t *pos = nullptr;
   GIFT_TRY(sc.get(&flag, R, "tile flags"));
   GIFT_TRY(sc.get(&pos, R + 1, "tile positions"));
-  k_tile_flags<Off><<<grid_for(R), kBlock, 0, st>>>(off, R, split, sh, flag);
+  k_tile_flags<Off><<<grid_for(R + 1), kBlock, 0, st>>>(off, R, split, sh, flag, narrow);
   GIFT_TRY(check_launch("k_tile_flags"));
   GIFT_TRY(scan_i32_to_i64(flag, pos, R, st));
   k_tile_scatter<<<grid_for(R > 0 ? R : 1), kBlock, 0, st>>>(flag, pos, R, split, tile_row,
@@ -123,8 +127,9 @@ gift_status tile_descs(const int32_t *tile_row, const int64_t *rp64, int64_t T, 
 }
 
 gift_status build_tiles64(const int64_t *off, int64_t R, int64_t split, TileShape sh,
-                          hipStream_t st, int32_t *tile_row, int64_t *counts_dev) {
-  return build_tiles_impl<int64_t>(off, R, split, sh, st, tile_row, counts_dev);
+                          hipStream_t st, int32_t *tile_row, int64_t *counts_dev,
+                          int32_t *narrow) {
+  return build_tiles_impl<int64_t>(off, R, split, sh, st, tile_row, counts_dev, narrow);
 }
 
 gift_status build_tiles64_pair(const int64_t *off, int64_t R, int64_t split, TileShape s0,
