@@ -110,6 +110,44 @@ def test_centred_16bit_keeps_bad_inputs_local(storage):
     assert np.array_equal(finite["f32"], finite[storage])
 
 
+def test_sixty_four_terms_float64():
+    """The largest filter the boundary takes: 64 terms, 8 self-loop weights
+    with orders 1..8 each and arbitrary weights alpha (not summing to 1),
+    against the oracle at the float64 bar; a 65th term is refused."""
+    import torch
+    import paper_2502_17632_amd as gift
+    nl = W.tiny(seed=5)
+    x = W.make_signal(nl, seed=5)
+    rng = np.random.default_rng(64)
+    sig = [s for s in (0.25, 0.5, 1.0, 1.5, 2.0, 3.0, 4.0, 6.0) for _ in range(8)]
+    order = [k for _ in range(8) for k in range(1, 9)]
+    alpha = list(rng.uniform(-0.5, 1.0, size=64))
+    y, ref, g, og = run_pair(nl, x, (sig, order, alpha), storage="f64", label="64 terms f64")
+    assert_close(y, ref, "f64", "64 terms f64")
+    xt = torch.tensor(x, device="cuda")
+    with pytest.raises(gift.GiftError):
+        gift.filter_placement(g, sig + [4.0], order + [1], alpha + [0.1], xt,
+                              out_dtype=torch.float64)
+    g.close()
+
+
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
+def test_sixty_four_sigma_groups_16bit(storage):
+    """64 terms with 64 distinct self-loop weights: the centring of 16-bit
+    iterates sums x and sqrt(d + sigma) for every group (four groups per
+    round of its reduction kernel, 16 rounds here), and the combine adds each
+    term's own c v back."""
+    nl = W.tiny(seed=6)
+    x = W.make_signal(nl, seed=6)
+    sig = [0.1 * (t + 1) for t in range(64)]
+    order = [1 + t % 3 for t in range(64)]
+    alpha = [1.0 / 64] * 64
+    y, ref, g, og = run_pair(nl, x, (sig, order, alpha), storage=storage,
+                             label=f"64 groups {storage}")
+    assert_close(y, ref, storage, f"64 groups {storage}")
+    g.close()
+
+
 def test_medium_two_over_m_paper_terms(medium):
     x = W.make_signal(medium, seed=3)
     y, ref, g, og = run_pair(medium, x, PAPER, storage="f32", star_threshold=16,
