@@ -293,9 +293,10 @@ def test_invalid_netlists_are_rejected():
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("storage", ["f32", "bf16"])
+@pytest.mark.parametrize("storage", ["f32", "bf16", "f16"])
 def test_large_full_size(storage):
-    """The large workload (2M + 20k cells, 2.1M nets), as the benchmark runs it."""
+    """The large workload (2M + 20k cells, 2.1M nets), as the benchmark runs it
+    (fixed cells kept at their input positions)."""
     nl = W.large()
     x = W.make_signal(nl)
     og = getattr(test_large_full_size, "_og", None)
@@ -304,6 +305,7 @@ def test_large_full_size(storage):
         og = O.build_netlist(nl, star_threshold=16)
         test_large_full_size._og = og
     y, ref, g, og = run_pair(nl, x, EQ5, storage=storage, star_threshold=16, og=og,
-                             label=f"large {storage}")
+                             fixed=nl.fixed, label=f"large {storage}")
     check_normalised(g, og, 4.0, storage)
     assert_close(y, ref, storage, f"large {storage}")
+    assert np.array_equal(y[nl.fixed != 0], x.astype(np.float32).astype(np.float64)[nl.fixed != 0])
