@@ -119,3 +119,30 @@ def test_malformed_device_csr_is_refused(case):
         gift.import_csr(*dev, sigmas=[4.0])
     assert ei.value.status == 1
     log(f"[import] malformed ({case}) refused: {ei.value}")
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_large_built_csr_imported_from_device(storage):
+    """The large design's graph (2.06M rows with its star nodes, 23.7M
+    entries), built from the netlist, exported and imported back from device
+    memory: the same CSR, degrees and stored normalised values bit for bit
+    (every row of the imported graph is a cell, so the star rows become
+    ordinary rows with the same weights)."""
+    import torch
+    import paper_2502_17632_amd as gift
+    nl = W.large()
+    gb = gift.build_graph(nl.num_cells, nl.net_ptr, nl.pin_cell, star_threshold=16,
+                          storage=storage, sigmas=[4.0])
+    rp, col, w, deg = gb.export()
+    log(f"[import] large built CSR R={len(rp) - 1} nnz={len(col)} storage={storage} (device)")
+    dev = (torch.tensor(rp.astype(np.int64), device="cuda"), torch.tensor(col, device="cuda"),
+           torch.tensor(w, device="cuda"))
+    gi = gift.import_csr(*dev, storage=storage, sigmas=[4.0])
+    rp2, col2, w2, deg2 = gi.export()
+    assert np.array_equal(rp2, rp) and np.array_equal(col2, col)
+    assert np.array_equal(w2.view(np.uint64), w.view(np.uint64))
+    assert np.array_equal(deg2.view(np.uint64), deg.view(np.uint64))
+    for u, v in zip(gb.export_normalised(4.0), gi.export_normalised(4.0)):
+        assert np.array_equal(u.view(np.uint64), v.view(np.uint64))
+    gb.close()
+    gi.close()
