@@ -9,9 +9,10 @@
 // A~_sigma = (D + sigma I)^-1/2 (A + sigma I) (D + sigma I)^-1/2
 // (eq. A_formulation) are rounded once to the storage type.
 //
-// Pipeline (all device work on the caller's stream):
-//   0. check net_ptr; tile the nets (consecutive nets, at most a few thousand
-//      pins per tile, long nets alone)
+// Pipeline (device work on the caller's stream and on a pooled side stream
+// that it forks to and joins with events):
+//   0. check net_ptr; tile the nets (consecutive nets, about a thousand pins
+//      per tile, long nets alone)
 //   1. per net tile, in LDS: distinct cells of every net, ascending (rank of
 //      each pin among the net's first occurrences); long nets by a block-wide
 //      bitonic sort in LDS or a merge sort through global memory.  The same
@@ -20,16 +21,18 @@
 //      entries from this net within the row (arbitrary order of the slices;
 //      the atomics overlap the LDS work of the net tiles)
 //   2. per net: clique or star, virtual id, weight
-//   3. exclusive scan of the row counts -> row slices; emit each pin's
-//      (col, net) keys into its slice
+//   3. exclusive scan of the row counts -> row slices and row tiles (side
+//      stream, beside step 2); emit each pin's (col, net) keys into its slice
 //   4. per row tile, in LDS: sort each row's keys by (col, net) (rank among
 //      the row's keys, which are distinct), count distinct columns.  The
 //      sorted order fixes every summation order below, so the result does
 //      not depend on the emission order
-//   5. scan of distinct counts -> row_ptr; SpMM row tiles
+//   5. scan of distinct counts -> row_ptr; the SpMM row tiles of both
+//      classes in one pass (side stream, beside step 6)
 //   6. per row tile, in LDS: merge runs of equal col (weights summed in
 //      ascending net id, float64), write col / w, degree summed in ascending
-//      col; star rows copy the net's sorted cells with weight M w(M)
+//      col; star rows copy the net's sorted cells with weight M w(M) (side
+//      stream)
 //   7. per sigma: s_i = 1/sqrt(d_i + sigma), a_ij = (w_ij s_i) s_j,
 //      diag_i = (sigma s_i) s_i
 #include <algorithm>
