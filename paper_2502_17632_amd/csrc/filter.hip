@@ -19,6 +19,12 @@
 // The same launch sequence serves one graph and a batch of graphs: in a batch
 // every tile names its graph, whose CSR, values, I/O and row offset in the
 // shared signal buffers come from a small device table.
+//
+// With BF16/F16 storage the iterates of each sigma group hold x - c v, v the
+// eigenvalue-1 eigenvector sqrt(d + sigma) of A~_sigma (Theorem 1 with the
+// self-loop) and c per graph and column, so the 16-bit rounding acts on the
+// placement's deviation rather than on its absolute coordinates; the last
+// pass adds c v back in its float64 combine (k_centre_part, k_centre_final).
 #include <cmath>
 #include <cstring>
 #include <mutex>
