@@ -112,13 +112,6 @@ KeyLayout key_layout(int64_t max_col, int64_t max_net, int64_t max_m) {
   return KeyLayout{32, 0, 0xffffffffull, 0};
 }
 
-// Fills seg[i] = k for every entry i of segment k (segments given by
-// local offsets loff[0..ns]); one thread per segment.
-__device__ __forceinline__ void fill_segment_ids(const int32_t *loff, int ns, uint16_t *seg) {
-  for (int k = threadIdx.x; k < ns; k += kBlock)
-    for (int i = loff[k]; i < loff[k + 1]; ++i) seg[i] = static_cast<uint16_t>(k);
-}
-
 // ---------------------------------------------------------------------------
 // 0. netlist checks
 // ---------------------------------------------------------------------------

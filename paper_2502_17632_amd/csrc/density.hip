@@ -1,10 +1,14 @@
 // Bin density of a placement (Section 2.2, eq. density_eq): the region
 // [xl, xh] x [yl, yh] is cut into nbx x nby equal bins and every bin gets the
 // overlap area of each object's rectangle (width w_v, height h_v, centred at
-// the object's position) with it.  One thread per object adds its overlaps
-// with the bins it covers.  The sums are kept in 64-bit fixed point (2^-40 of
-// a bin's area per unit), so the atomic additions are exact and the result
-// does not depend on their order; the map is then converted to float64.
+// the object's position) with it.  A block takes a contiguous range of
+// objects, a thread per object adds its overlaps with the bins it covers into
+// an LDS table of the block's bins, and the block then adds each of its bins
+// to the map once (placements crowd many objects into few bins, and device
+// atomics on one address serialise).  The sums are kept in 64-bit fixed
+// point (2^-40 of a bin's area per unit), so the additions are exact and the
+// result does not depend on their order; the map is then converted to
+// float64.
 #include <cmath>
 
 #include "common.h"
@@ -31,9 +35,11 @@ struct DensityArgs {
   unsigned long long *acc;  // nby x nbx fixed-point sums
 };
 
-__global__ __launch_bounds__(kBlock) void k_density(DensityArgs a) {
-  const int64_t v = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
-  if (v >= a.n) return;
+constexpr int kDensityBlocks = 2048;
+constexpr int kDensitySlots = 1024;
+
+__device__ __forceinline__ void add_object(const DensityArgs &a, int64_t v,
+                                           LdsHash<unsigned long long, kDensitySlots> &h) {
   const double cx = load_pos(a.x, a.dtype, v * a.ld), cy = load_pos(a.x, a.dtype, v * a.ld + 1);
   const double wv = a.w ? to_global(a.w)[v] : a.w0, hv = a.h ? to_global(a.h)[v] : a.h0;
   if (!(wv > 0.0) || !(hv > 0.0) || !std::isfinite(cx) || !std::isfinite(cy)) return;
@@ -58,9 +64,21 @@ __global__ __launch_bounds__(kBlock) void k_density(DensityArgs a) {
       if (lx <= 0.0) continue;
       const unsigned long long q =
           static_cast<unsigned long long>(llrint(lx * ly * inv_area * kFixScale));
-      atomicAdd(a.acc + static_cast<int64_t>(j) * a.nbx + i, q);
+      h.add(j * a.nbx + i, q, a.acc);
     }
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_density(DensityArgs a) {
+  __shared__ LdsHash<unsigned long long, kDensitySlots> h;
+  h.clear();
+  __syncthreads();
+  const int64_t per = (a.n + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = static_cast<int64_t>(blockIdx.x) * per;
+  const int64_t hi = lo + per < a.n ? lo + per : a.n;
+  for (int64_t v = lo + threadIdx.x; v < hi; v += kBlock) add_object(a, v, h);
+  __syncthreads();
+  h.flush(a.acc);
 }
 
 __global__ void k_density_out(const unsigned long long *acc, int64_t nb, double area,
@@ -161,7 +179,9 @@ extern "C" gift_status gift_bin_density(const void *x, int64_t num_objects, int6
   if (num_objects > 0) {
     DensityArgs a{x, num_objects, ld, dtype, widths, heights, w0, h0, xl, yl, bw, bh, nbx, nby,
                   acc};
-    k_density<<<grid_for(num_objects), kBlock, 0, st>>>(a);
+    const int64_t blocks = (num_objects + kBlock - 1) / kBlock;
+    k_density<<<static_cast<unsigned>(blocks < kDensityBlocks ? blocks : kDensityBlocks), kBlock,
+                0, st>>>(a);
     GIFT_TRY(check_launch("k_density"));
   }
   k_density_out<<<grid_for(nb), kBlock, 0, st>>>(acc, nb, bw * bh, density);

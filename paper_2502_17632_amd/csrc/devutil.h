@@ -44,6 +44,75 @@ __device__ __forceinline__ T block_sum(T v, T *tmp) {
   return total;
 }
 
+// Fills seg[i] = k for every entry i of segment k (segments given by
+// local offsets loff[0..ns]); one thread per segment.
+__device__ __forceinline__ void fill_segment_ids(const int32_t *loff, int ns, uint16_t *seg) {
+  for (int k = threadIdx.x; k < ns; k += kBlock)
+    for (int i = loff[k]; i < loff[k + 1]; ++i) seg[i] = static_cast<uint16_t>(k);
+}
+
+// Sum of part[b * stride] over b < nb by one block, in a fixed order:
+// thread t adds the contiguous run [t * per, (t + 1) * per) in order, then a
+// fixed tree adds the threads' sums.  The same order on every run, and every
+// thread's loads are independent of each other (no serial chain over nb).
+// `red` is kBlock doubles of LDS; every thread gets the result.
+__device__ __forceinline__ double block_sum_strided(const double *part, int64_t nb,
+                                                    int64_t stride, double *red) {
+  const int64_t per = (nb + kBlock - 1) / kBlock;
+  const int64_t b0 = static_cast<int64_t>(threadIdx.x) * per;
+  const int64_t b1 = b0 + per < nb ? b0 + per : nb;
+  double s = 0.0;
+#pragma unroll 4
+  for (int64_t b = b0; b < b1; ++b) s += part[b * stride];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// Per-block accumulation of (key, amount) pairs before they reach global
+// memory: an LDS table of S slots (S a power of two), open addressing with
+// linear probing over at most kProbes slots; a pair that finds no slot goes
+// straight to global memory.  Many additions to one key inside a block thus
+// cost one global atomic (flush), not one each: device-scope atomics on one
+// address serialise in the memory system, LDS ones stay inside the CU.
+// Integer amounts only, so the totals do not depend on the order.  Usage:
+// clear(); __syncthreads(); add(...)...; __syncthreads(); flush().
+template <typename V, int S>
+struct LdsHash {
+  static_assert((S & (S - 1)) == 0, "slot count must be a power of two");
+  static constexpr int kProbes = 8;
+  int32_t key[S];
+  V val[S];
+  __device__ __forceinline__ void clear() {
+    for (int k = threadIdx.x; k < S; k += blockDim.x) {
+      key[k] = -1;
+      val[k] = 0;
+    }
+  }
+  __device__ __forceinline__ void add(int32_t k, V v, V *global) {
+    uint32_t h = (static_cast<uint32_t>(k) * 2654435761u) >> 7 & (S - 1);
+    for (int p = 0; p < kProbes; ++p) {
+      const int32_t prev = atomicCAS(&key[h], -1, k);
+      if (prev == -1 || prev == k) {
+        atomicAdd(&val[h], v);
+        return;
+      }
+      h = (h + 1) & (S - 1);
+    }
+    atomicAdd(global + k, v);
+  }
+  __device__ __forceinline__ void flush(V *global) {
+    for (int k = threadIdx.x; k < S; k += blockDim.x)
+      if (key[k] >= 0 && val[k] != 0) atomicAdd(global + key[k], val[k]);
+  }
+};
+
 // Ascending bitonic sort of s[0..n) in LDS, n a power of two.
 template <typename K>
 __device__ void lds_bitonic_sort(K *s, int n) {

@@ -90,9 +90,23 @@ __global__ void k_cc_sweep(const int32_t *row_ptr, const int32_t *col, int64_t R
   if (ch) atomicOr(changed, 1u);
 }
 
-__global__ void k_cc_count(const int32_t *label, int64_t N, int32_t *count) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < N) atomicAdd(count + label[i], 1);
+// Component sizes: count[label[i]] += 1 over the cell rows.  Block b takes a
+// contiguous range of cells and adds into an LDS table first: nearly every
+// cell of a placement graph is in one component, and one address taking N
+// device atomics in a row costs milliseconds.
+constexpr int kCountSlots = 1024;
+__global__ __launch_bounds__(kBlock) void k_cc_count(const int32_t *label, int64_t N,
+                                                     int32_t *count) {
+  __shared__ LdsHash<int32_t, kCountSlots> h;
+  h.clear();
+  __syncthreads();
+  const int64_t per = (N + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = static_cast<int64_t>(blockIdx.x) * per;
+  const int64_t hi = lo + per < N ? lo + per : N;
+  const gptr<const int32_t> lb = to_global(label);
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) h.add(lb[i], 1, count);
+  __syncthreads();
+  h.flush(count);
 }
 
 // key = count << 32 | (2^31 - 1 - label): the largest key is the largest
@@ -120,13 +134,9 @@ __global__ __launch_bounds__(kBlock) void k_cc_best(const int32_t *count, int64_
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-// out[0] = the best key; out[1] = bits of 2 max degree over the giant
-// component's cells (an upper bound on lambda_max by Gershgorin).
-__global__ __launch_bounds__(kBlock) void k_cc_pick(const int64_t *part, int nb,
-                                                    const int32_t *label, const double *deg,
-                                                    int64_t N, int64_t *out) {
+// out[0] = the best key (one block over the per-block maxima).
+__global__ __launch_bounds__(kBlock) void k_cc_key(const int64_t *part, int nb, int64_t *out) {
   __shared__ int64_t red[kBlock];
-  __shared__ double dred[kBlock];
   int64_t best = 0;
   for (int b = threadIdx.x; b < nb; b += kBlock) best = part[b] > best ? part[b] : best;
   red[threadIdx.x] = best;
@@ -136,21 +146,48 @@ __global__ __launch_bounds__(kBlock) void k_cc_pick(const int64_t *part, int nb,
       red[threadIdx.x] = red[threadIdx.x + off];
     __syncthreads();
   }
-  const int64_t key = red[0];
-  const int32_t g = static_cast<int32_t>(0x7fffffff - (key & 0xffffffff));
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+// dpart[b] = the largest degree over block b's range of the giant
+// component's cells (the component named by key[0]).
+__global__ __launch_bounds__(kBlock) void k_cc_dmax(const int32_t *label, const double *deg,
+                                                    int64_t N, const int64_t *key,
+                                                    double *dpart) {
+  __shared__ double red[kBlock];
+  const int32_t g = static_cast<int32_t>(0x7fffffff - (key[0] & 0xffffffff));
+  const int64_t per = (N + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = static_cast<int64_t>(blockIdx.x) * per;
+  const int64_t hi = lo + per < N ? lo + per : N;
   double dmax = 0.0;
-  for (int64_t i = threadIdx.x; i < N; i += kBlock)
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock)
     if (label[i] == g) dmax = deg[i] > dmax ? deg[i] : dmax;
-  dred[threadIdx.x] = dmax;
+  red[threadIdx.x] = dmax;
   __syncthreads();
   for (int off = kBlock / 2; off > 0; off >>= 1) {
-    if (threadIdx.x < off && dred[threadIdx.x + off] > dred[threadIdx.x])
-      dred[threadIdx.x] = dred[threadIdx.x + off];
+    if (threadIdx.x < off && red[threadIdx.x + off] > red[threadIdx.x])
+      red[threadIdx.x] = red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) dpart[blockIdx.x] = red[0];
+}
+
+// out[1] = bits of 2 max degree over the giant component's cells (an upper
+// bound on lambda_max by Gershgorin).  Maxima are exact, so the split over
+// blocks does not change the value.
+__global__ __launch_bounds__(kBlock) void k_cc_bound(const double *dpart, int nb, int64_t *out) {
+  __shared__ double red[kBlock];
+  double dmax = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kBlock) dmax = dpart[b] > dmax ? dpart[b] : dmax;
+  red[threadIdx.x] = dmax;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off && red[threadIdx.x + off] > red[threadIdx.x])
+      red[threadIdx.x] = red[threadIdx.x + off];
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    out[0] = key;
-    const double b = 2.0 * dred[0];
+    const double b = 2.0 * red[0];
     int64_t bits;
     memcpy(&bits, &b, 8);
     out[1] = bits;
@@ -199,10 +236,34 @@ __global__ __launch_bounds__(kBlock) void k_eig_apply(const int32_t *row_ptr, co
   double o[K] = {};
   if (label[i] == giant) {
     double acc[K] = {};
+    const gptr<const int32_t> cl = to_global(col);
+    const gptr<const double> wv = to_global(w);
     const int32_t p0 = row_ptr[i], p1 = row_ptr[i + 1];
-    for (int32_t p = p0; p < p1; ++p) {
-      const int64_t j = col[p];
-      const double wj = w[p];
+    int32_t p = p0;
+    // four entries at a time, their loads issued before the adds (which keep
+    // the entry order of the plain loop)
+    for (; p + 3 < p1; p += 4) {
+      int64_t j[4];
+      double wj[4], v[4][K];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        j[u] = cl[p + u];
+        wj[u] = wv[p + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const gptr<const double> src = j[u] < N ? xg + j[u] * K : eg + (j[u] - N) * K;
+#pragma unroll
+        for (int q = 0; q < K; ++q) v[u][q] = src[q];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < K; ++q) acc[q] += wj[u] * v[u][q];
+    }
+    for (; p < p1; ++p) {
+      const int64_t j = cl[p];
+      const double wj = wv[p];
       const gptr<const double> src = j < N ? xg + j * K : eg + (j - N) * K;
 #pragma unroll
       for (int q = 0; q < K; ++q) acc[q] += wj * src[q];
@@ -298,13 +359,13 @@ __global__ __launch_bounds__(kBlock) void k_eig_resid(const double *x, const dou
     }
   block_sums<K>(s, red, part);
 }
-// out[q] = sum over b of part[b * M + q], in block order (one thread per q)
-__global__ void k_eig_sum(const double *part, int nb, int M, double *out) {
-  const int q = threadIdx.x;
-  if (q >= M) return;
-  double s = 0.0;
-  for (int b = 0; b < nb; ++b) s += part[b * M + q];
-  out[q] = s;
+// out[q] = sum over b of part[b * M + q]: block q, in the fixed order of
+// block_sum_strided
+__global__ __launch_bounds__(kBlock) void k_eig_sum(const double *part, int nb, int M,
+                                                    double *out) {
+  __shared__ double red[kBlock];
+  const double s = block_sum_strided(part + blockIdx.x, nb, M, red);
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
 // A reproducible start: a hash of (seed, row, column) mapped to [-1, 1) on
@@ -584,13 +645,13 @@ struct EigenRun {
   gift_status gram(const double *a, const double *b) {
     k_eig_gram<<<kRedBlocks, kBlock, 0, st>>>(a, b, N, part);
     GIFT_TRY(check_launch("k_eig_gram"));
-    k_eig_sum<<<1, kWave, 0, st>>>(part, kRedBlocks, K * K, small + kG);
+    k_eig_sum<<<K * K, kBlock, 0, st>>>(part, kRedBlocks, K * K, small + kG);
     return check_launch("k_eig_sum");
   }
   gift_status deflate(double *x) {
     k_eig_colsum<<<kRedBlocks, kBlock, 0, st>>>(x, label, giant, N, part);
     GIFT_TRY(check_launch("k_eig_colsum"));
-    k_eig_sum<<<1, kWave, 0, st>>>(part, kRedBlocks, K, small + kSum);
+    k_eig_sum<<<K, kBlock, 0, st>>>(part, kRedBlocks, K, small + kSum);
     GIFT_TRY(check_launch("k_eig_sum"));
     k_eig_deflate<<<grid_for(N), kBlock, 0, st>>>(x, label, giant, N, small, count);
     return check_launch("k_eig_deflate");
@@ -619,7 +680,7 @@ struct EigenRun {
     GIFT_TRY(check_launch("k_eig_mul"));
     k_eig_resid<<<kRedBlocks, kBlock, 0, st>>>(x, w, small, N, part);
     GIFT_TRY(check_launch("k_eig_resid"));
-    k_eig_sum<<<1, kWave, 0, st>>>(part, kRedBlocks, K, small + kRes);
+    k_eig_sum<<<K, kBlock, 0, st>>>(part, kRedBlocks, K, small + kRes);
     GIFT_TRY(check_launch("k_eig_sum"));
     int64_t bits[3 * K];
     static_assert(kRes == kTheta + 2 * K, "Ritz values and residuals are read together");
@@ -675,15 +736,21 @@ extern "C" gift_status gift_eigen_placement(const gift_graph *g, double tol, int
 
   // 2. the giant component and the spectral bound
   int64_t *bpart = nullptr, *pick = nullptr;
+  double *dpart = nullptr;
   GIFT_TRY(sc.get(&bpart, kRedBlocks, "component maxima"));
+  GIFT_TRY(sc.get(&dpart, kRedBlocks, "degree maxima"));
   GIFT_TRY(sc.get(&pick, 2, "giant component"));
   GIFT_HIP(hipMemsetAsync(count, 0, N * 4, st));
-  k_cc_count<<<grid_for(N), kBlock, 0, st>>>(label, N, count);
+  k_cc_count<<<kRedBlocks, kBlock, 0, st>>>(label, N, count);
   GIFT_TRY(check_launch("k_cc_count"));
   k_cc_best<<<kRedBlocks, kBlock, 0, st>>>(count, N, bpart);
   GIFT_TRY(check_launch("k_cc_best"));
-  k_cc_pick<<<1, kBlock, 0, st>>>(bpart, kRedBlocks, label, g->deg, N, pick);
-  GIFT_TRY(check_launch("k_cc_pick"));
+  k_cc_key<<<1, kBlock, 0, st>>>(bpart, kRedBlocks, pick);
+  GIFT_TRY(check_launch("k_cc_key"));
+  k_cc_dmax<<<kRedBlocks, kBlock, 0, st>>>(label, g->deg, N, pick, dpart);
+  GIFT_TRY(check_launch("k_cc_dmax"));
+  k_cc_bound<<<1, kBlock, 0, st>>>(dpart, kRedBlocks, pick);
+  GIFT_TRY(check_launch("k_cc_bound"));
   int64_t hp[2];
   GIFT_TRY(read_back(st, nullptr, pick, nullptr, 2, hp));
   const int64_t cells = hp[0] >> 32;

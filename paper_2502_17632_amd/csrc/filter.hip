@@ -856,14 +856,13 @@ __device__ __forceinline__ void cg_block_sum(double (&v)[C], double *red, double
   }
 }
 
-// out[q] = sum of part[b * C + q] over b in order.
+// out[q] = sum of part[b * C + q] over b < nb: block q, in the fixed order of
+// block_sum_strided.
 template <int C>
-__global__ void k_cg_reduce(const double *part, int nb, double *out) {
-  const int q = threadIdx.x;
-  if (q >= C) return;
-  double s = 0.0;
-  for (int b = 0; b < nb; ++b) s += part[b * C + q];
-  out[q] = s;
+__global__ __launch_bounds__(kBlock) void k_cg_reduce(const double *part, int nb, double *out) {
+  __shared__ double red[kBlock];
+  const double s = block_sum_strided(part + blockIdx.x, nb, C, red);
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
 // x = 0, r = p = b; part = b . b
@@ -1003,7 +1002,7 @@ gift_status exact_chunk(const gift_graph *g, const FilterPlan &pl, double tol, i
   GIFT_TRY(check_launch("k_prep"));
   k_cg_init<D, C><<<nb, kBlock, 0, st>>>(b, x, r, p, R, part);
   GIFT_TRY(check_launch("k_cg_init"));
-  k_cg_reduce<C><<<1, kWave, 0, st>>>(part, nb, bb);
+  k_cg_reduce<C><<<C, kBlock, 0, st>>>(part, nb, bb);
   GIFT_TRY(check_launch("k_cg_reduce"));
   GIFT_HIP(hipMemcpyAsync(rho[0], bb, sizeof(double) * C, hipMemcpyDeviceToDevice, st));
   const LaunchArgs l = launch_args(pl, pl.groups.front(), false);
@@ -1017,10 +1016,10 @@ gift_status exact_chunk(const gift_graph *g, const FilterPlan &pl, double tol, i
                           static_cast<const void *>(p), static_cast<void *>(q), FinalArgs{}));
     k_cg_q<D, C><<<nb, kBlock, 0, st>>>(p, q, R, part);
     GIFT_TRY(check_launch("k_cg_q"));
-    k_cg_reduce<C><<<1, kWave, 0, st>>>(part, nb, pq);
+    k_cg_reduce<C><<<C, kBlock, 0, st>>>(part, nb, pq);
     k_cg_update<D, C><<<nb, kBlock, 0, st>>>(x, r, p, q, rho[cur], pq, R, part);
     GIFT_TRY(check_launch("k_cg_update"));
-    k_cg_reduce<C><<<1, kWave, 0, st>>>(part, nb, rho[cur ^ 1]);
+    k_cg_reduce<C><<<C, kBlock, 0, st>>>(part, nb, rho[cur ^ 1]);
     k_cg_p<D, C><<<nb, kBlock, 0, st>>>(r, p, rho[cur], rho[cur ^ 1], R);
     GIFT_TRY(check_launch("k_cg_p"));
     cur ^= 1;

@@ -93,3 +93,28 @@ def test_metrics_are_deterministic_and_check_arguments():
     with pytest.raises(ValueError):
         gift.evaluate_placement(g, x[:10])
     g.close()
+
+
+@pytest.mark.parametrize("threshold", [16, 0])
+def test_metrics_with_a_ragged_column_count(threshold):
+    """Seven columns (a full group of four and a ragged three) on a design
+    with nets of up to 1000 pins: star rows and, without stars, clique rows
+    longer than one row tile's limit, and nets long enough to be taken by a
+    whole wave, all against the oracle."""
+    import torch
+    import paper_2502_17632_amd as gift
+    nl = W.sized(30_000, seed=21)
+    x = np.random.default_rng(21).normal(scale=50.0, size=(nl.num_cells, 7))
+    og = O.build_netlist(nl, star_threshold=threshold)
+    g = gift.build_graph(nl.num_cells, nl.net_ptr, nl.pin_cell, star_threshold=threshold)
+    xt = torch.tensor(x, dtype=torch.float64, device="cuda")
+    m = gift.evaluate_placement(g, xt, nl.net_ptr, nl.pin_cell)
+    S, n2, h = og.evaluate(x)
+    og.close()
+    g.close()
+    sizes = np.diff(nl.net_ptr)
+    log(f"[eval] 7 columns, threshold {threshold}: longest net {sizes.max()} pins; "
+        f"S {m['smoothness'][:2]}.. (oracle {S[:2]}..)")
+    assert np.all(rel(m["smoothness"], S) < TOL)
+    assert np.all(rel(m["norm2"], n2) < TOL)
+    assert np.all(rel(m["hpwl"], h) < TOL)
