@@ -70,8 +70,13 @@ struct LaunchArgs {
   int32_t identity_map;
 };
 
+// Without the per-XCD layout, blocks take the tile list from its end, in
+// chunks dealt to the XCDs: the star rows' tiles come last in the list, and
+// each of their rows gathers its net's cells from around the design, so they
+// start first instead of forming the launch's tail.  Every row is computed
+// by the same arithmetic whichever block takes it.
 __device__ __forceinline__ uint32_t tile_of_block(const LaunchArgs &l) {
-  return l.identity_map ? blockIdx.x : xcd_remap(blockIdx.x, gridDim.x);
+  return l.identity_map ? blockIdx.x : gridDim.x - 1 - xcd_remap(blockIdx.x, gridDim.x);
 }
 
 template <bool kBatch>
