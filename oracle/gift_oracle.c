@@ -30,11 +30,15 @@
  *   - the degree excludes the self-loop, which enters only through D + sigma I;
  *   - t_i = d_i + sigma = 0 (isolated cell, sigma = 0) gives s_i = 0, i.e. the
  *     row and column vanish;
- *   - star expansion: virtual node v = N + (number of star nets before e), edge
- *     weight gamma = M * w(M) between v and every cell of the net (rounded once
- *     to FP64: M/(M-1) or exactly 2); virtual rows carry the self-loop sigma
- *     like every row, start at the mean of their cells' signal and are not
- *     returned;
+ *   - star expansion: edge weight gamma = M * w(M) between the net's virtual
+ *     node and every cell of the net (rounded once to FP64: M/(M-1) or
+ *     exactly 2); virtual rows carry the self-loop sigma like every row,
+ *     start at the mean of their cells' signal and are not returned.  The
+ *     virtual nodes are rows N..N+V-1; the paper fixes no labelling of them,
+ *     and two are provided (oracle_build_ordered): ascending net id, or
+ *     ascending median cell of the net (the distinct cell at index M/2 of the
+ *     ascending list), ties by ascending net id.  The two graphs are one
+ *     graph under a relabelling of the virtual rows;
  *   - the combine is an FP64 sum in term order.
  * Summation orders are fixed so the structure, weights and degrees have a
  * single correct bit pattern: duplicates are summed in ascending net id,
@@ -49,6 +53,7 @@
 
 enum { ORACLE_OK = 0, ORACLE_EINVAL = 1, ORACLE_ENOMEM = 2 };
 enum { ORACLE_W_INV_M1 = 0, ORACLE_W_TWO_OVER_M = 1 };
+enum { ORACLE_STARS_BY_NET = 0, ORACLE_STARS_BY_MEDIAN = 1 };
 
 typedef struct {
   int64_t num_cells;   /* N */
@@ -83,6 +88,17 @@ static int cmp_triple(const void *a, const void *b) {
   return (x->net > y->net) - (x->net < y->net);
 }
 
+/* (median cell, net) of a star net; ordered by median, then net */
+typedef struct {
+  int64_t median, net;
+} star_key;
+
+static int cmp_star_key(const void *a, const void *b) {
+  const star_key *x = (const star_key *)a, *y = (const star_key *)b;
+  if (x->median != y->median) return (x->median > y->median) - (x->median < y->median);
+  return (x->net > y->net) - (x->net < y->net);
+}
+
 static double clique_weight(int64_t m, int model) {
   if (model == ORACLE_W_TWO_OVER_M) return 2.0 / (double)m;
   return 1.0 / (double)(m - 1);
@@ -105,11 +121,16 @@ void oracle_free(oracle_graph *g) {
   free(g);
 }
 
-/* Steps O1-O4: netlist -> canonical CSR of A and degrees. */
-int oracle_build(int64_t num_cells, int64_t num_nets, int64_t num_pins,
-                 const int64_t *net_ptr, const int32_t *pin_cell,
-                 int weight_model, int64_t star_threshold, oracle_graph **out) {
+/* Steps O1-O4: netlist -> canonical CSR of A and degrees, with the virtual
+ * rows labelled by star_order (ORACLE_STARS_BY_NET or ORACLE_STARS_BY_MEDIAN,
+ * see the header). */
+int oracle_build_ordered(int64_t num_cells, int64_t num_nets, int64_t num_pins,
+                         const int64_t *net_ptr, const int32_t *pin_cell,
+                         int weight_model, int64_t star_threshold, int star_order,
+                         oracle_graph **out) {
   *out = NULL;
+  if (star_order != ORACLE_STARS_BY_NET && star_order != ORACLE_STARS_BY_MEDIAN)
+    return ORACLE_EINVAL;
   if (num_cells < 0 || num_nets < 0 || num_pins < 0) return ORACLE_EINVAL;
   if (weight_model != ORACLE_W_INV_M1 && weight_model != ORACLE_W_TWO_OVER_M)
     return ORACLE_EINVAL;
@@ -156,16 +177,35 @@ int oracle_build(int64_t num_cells, int64_t num_nets, int64_t num_pins,
   triple *t = (triple *)malloc(sizeof(triple) * (size_t)(z > 0 ? z : 1));
   if (!g->virt_net || !t) { free(t); oracle_free(g); return ORACLE_ENOMEM; }
 
+  /* The virtual row of every star net: its rank among the star nets in net
+   * order, or in (median cell, net) order. */
+  int64_t *vrank = (int64_t *)malloc(sizeof(int64_t) * (size_t)(num_nets > 0 ? num_nets : 1));
+  star_key *sk = (star_key *)malloc(sizeof(star_key) * (size_t)(num_star > 0 ? num_star : 1));
+  if (!vrank || !sk) { free(vrank); free(sk); free(t); oracle_free(g); return ORACLE_ENOMEM; }
+  {
+    int64_t ns = 0;
+    for (int64_t e = 0; e < num_nets; ++e) {
+      int64_t a = g->ucell_ptr[e], m = g->ucell_ptr[e + 1] - a;
+      if (m < 2 || !(star_threshold > 0 && m > star_threshold)) continue;
+      sk[ns].median = star_order == ORACLE_STARS_BY_MEDIAN ? g->ucell[a + m / 2] : 0;
+      sk[ns].net = e;
+      ++ns;
+    }
+    if (star_order == ORACLE_STARS_BY_MEDIAN) qsort(sk, (size_t)ns, sizeof(star_key), cmp_star_key);
+    for (int64_t r = 0; r < ns; ++r) vrank[sk[r].net] = r;
+  }
+  free(sk);
+
   /* O2: expansion into directed (row, col, net, weight) entries. */
-  int64_t k = 0, v = 0;
+  int64_t k = 0;
   for (int64_t e = 0; e < num_nets; ++e) {
     int64_t a = g->ucell_ptr[e], m = g->ucell_ptr[e + 1] - a;
     const int32_t *c = g->ucell + a;
     if (m < 2) continue;
     if (star_threshold > 0 && m > star_threshold) {
-      int32_t vid = (int32_t)(num_cells + v);
+      int32_t vid = (int32_t)(num_cells + vrank[e]);
       double gam = star_weight(m, weight_model);
-      g->virt_net[v++] = (int32_t)e;
+      g->virt_net[vrank[e]] = (int32_t)e;
       for (int64_t i = 0; i < m; ++i) {
         t[k].row = c[i]; t[k].col = vid; t[k].net = (int32_t)e; t[k].w = gam; ++k;
         t[k].row = vid; t[k].col = c[i]; t[k].net = (int32_t)e; t[k].w = gam; ++k;
@@ -179,6 +219,8 @@ int oracle_build(int64_t num_cells, int64_t num_nets, int64_t num_pins,
         }
     }
   }
+
+  free(vrank);
 
   /* O3: sort by (row, col, net); merge equal (row, col) left to right. */
   qsort(t, (size_t)z, sizeof(triple), cmp_triple);
@@ -213,6 +255,14 @@ int oracle_build(int64_t num_cells, int64_t num_nets, int64_t num_pins,
   }
   *out = g;
   return ORACLE_OK;
+}
+
+/* Steps O1-O4 with the virtual rows in ascending net order. */
+int oracle_build(int64_t num_cells, int64_t num_nets, int64_t num_pins,
+                 const int64_t *net_ptr, const int32_t *pin_cell,
+                 int weight_model, int64_t star_threshold, oracle_graph **out) {
+  return oracle_build_ordered(num_cells, num_nets, num_pins, net_ptr, pin_cell, weight_model,
+                              star_threshold, ORACLE_STARS_BY_NET, out);
 }
 
 void oracle_sizes(const oracle_graph *g, int64_t *sizes /* [N, V, R, nnz] */) {

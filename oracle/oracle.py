@@ -30,6 +30,9 @@ def load(path: Optional[str] = None):
     vp = C.c_void_p
     lib.oracle_build.argtypes = [i64, i64, i64, vp, vp, C.c_int, i64, C.POINTER(vp)]
     lib.oracle_build.restype = C.c_int
+    lib.oracle_build_ordered.argtypes = [i64, i64, i64, vp, vp, C.c_int, i64, C.c_int,
+                                         C.POINTER(vp)]
+    lib.oracle_build_ordered.restype = C.c_int
     lib.oracle_free.argtypes = [vp]
     lib.oracle_free.restype = None
     lib.oracle_sizes.argtypes = [vp, vp]
@@ -163,16 +166,25 @@ class OracleGraph:
         return S, n2, h
 
 
+STAR_ORDERS = {"net": 0, "median": 1}
+
+
 def build_graph(num_cells: int, net_ptr: np.ndarray, pin_cell: np.ndarray, *,
                 weight_model: int = W_INV_M1, star_threshold: int = 0,
-                lib=None) -> OracleGraph:
+                star_order: str = "net", lib=None) -> OracleGraph:
+    """Steps O1-O4 (see oracle_build_ordered).  star_order labels the
+    virtual rows N..N+V-1: "net" in ascending net id, "median" in ascending
+    median cell of the net (index M/2 of its ascending distinct cells), ties
+    by net id."""
     lib = lib or load()
     net_ptr = np.ascontiguousarray(net_ptr, dtype=np.int64)
     pin_cell = np.ascontiguousarray(pin_cell, dtype=np.int32)
     h = C.c_void_p()
-    rc = lib.oracle_build(int(num_cells), net_ptr.shape[0] - 1, pin_cell.shape[0],
-                          _ptr(net_ptr), _ptr(pin_cell), int(weight_model),
-                          int(star_threshold), C.byref(h))
+    if star_order not in STAR_ORDERS:
+        raise OracleError(f"star_order must be one of {sorted(STAR_ORDERS)}")
+    rc = lib.oracle_build_ordered(int(num_cells), net_ptr.shape[0] - 1, pin_cell.shape[0],
+                                  _ptr(net_ptr), _ptr(pin_cell), int(weight_model),
+                                  int(star_threshold), STAR_ORDERS[star_order], C.byref(h))
     if rc:
         raise OracleError(f"oracle_build failed ({rc})")
     sizes = np.zeros(4, dtype=np.int64)

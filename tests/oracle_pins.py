@@ -275,6 +275,63 @@ def pin_star_start_value(lib):
         g.close()
 
 
+def pin_star_order_golden(lib):
+    """Labelling of the virtual rows by the median cell of their net (the
+    paper leaves the labelling free).  Ten cells, T = 2: the star nets and
+    the medians of their ascending distinct cells (index M/2) are
+    e0 {7,8,9} -> 8, e1 {0,1,2} -> 1, e2 {4,5,6} -> 5, e3 {1,2,3} -> 2 (its
+    pins repeat a cell) and e5 {3,4,5,6} -> 5 (M even: the upper of the two
+    middle cells); e4 {0,9} is a clique.  By median, ties by net id: e1, e3,
+    e2, e5, e0.  In net order: e0, e1, e2, e3, e5."""
+    nets = [[9, 7, 8], [2, 0, 1], [6, 4, 5], [3, 2, 1, 2], [0, 9], [6, 5, 4, 3]]
+    net_ptr = np.cumsum([0] + [len(n) for n in nets]).astype(np.int64)
+    pins = np.array([c for n in nets for c in n], dtype=np.int32)
+    for order, exp in (("median", [1, 3, 2, 5, 0]), ("net", [0, 1, 2, 3, 5])):
+        g = O.build_graph(10, net_ptr, pins, star_threshold=2, star_order=order, lib=lib)
+        assert g.num_virtual == 5 and g.virt_net.tolist() == exp, (order, g.virt_net)
+        for v, e in enumerate(exp):  # each virtual row holds its net's cells
+            cells = sorted(set(nets[e]))
+            assert g.col[g.row_ptr[10 + v]:g.row_ptr[11 + v]].tolist() == cells, (order, v)
+        g.close()
+
+
+def pin_star_order_relabels(lib):
+    """Both labellings give one graph: on generated netlists with star nets,
+    the median-labelled CSR equals the net-labelled one with the virtual rows
+    and columns relabelled, weights bit for bit; degrees of virtual rows are
+    bit-equal, those of cells (a sum over the row in ascending column, whose
+    order the relabelling changes) equal to 1e-15; the medians of the virtual
+    rows never decrease, and equal medians come in ascending net id."""
+    rng = np.random.default_rng(11)
+    for seed, thr in ((5, 4), (6, 8)):
+        nl = W.make_netlist(400, 4, 420, cap=60, window=64, seed=seed)
+        a = O.build_netlist(nl, star_threshold=thr, lib=lib)
+        b = O.build_netlist(nl, star_threshold=thr, star_order="median", lib=lib)
+        n, v = a.num_cells, a.num_virtual
+        assert v > 10 and b.num_virtual == v
+        pos = {int(e): i for i, e in enumerate(a.virt_net)}
+        new_of_old = np.arange(n + v)
+        for i, e in enumerate(b.virt_net):
+            new_of_old[n + pos[int(e)]] = n + i
+        for r in rng.permutation(n + v)[:200].tolist() + list(range(n, n + v)):
+            ra = slice(a.row_ptr[r], a.row_ptr[r + 1])
+            rb = slice(b.row_ptr[new_of_old[r]], b.row_ptr[new_of_old[r] + 1])
+            ca, wa = new_of_old[a.col[ra]], a.w[ra]
+            o = np.argsort(ca, kind="stable")
+            assert np.array_equal(ca[o], b.col[rb]), r
+            assert np.array_equal(wa[o].view(np.uint64), b.w[rb].view(np.uint64)), r
+            if r >= n:
+                assert a.deg[r] == b.deg[new_of_old[r]], r
+            else:
+                assert abs(a.deg[r] - b.deg[r]) <= 1e-15 * a.deg[r], r
+        lens = np.diff(b.row_ptr[n:])
+        med = b.col[b.row_ptr[n:-1] + lens // 2].astype(np.int64)
+        key = med * (1 << 32) + b.virt_net.astype(np.int64)
+        assert np.all(np.diff(key) > 0)
+        a.close()
+        b.close()
+
+
 def pin_generated_invariants(lib):
     """On a generated clique-model netlist: weights are symmetric bit for bit,
     with w = 1/(M-1) every cell's degree is the number of nets it is on, and
@@ -629,7 +686,7 @@ def pin_import_csr(lib):
 ALL_PINS = [pin_golden_two_cell, pin_clique_closed_form, pin_hand_built,
             pin_brute_force_structure, pin_spectral, pin_theorem1_fixed_point,
             pin_spectrum, pin_isolated_and_fixed, pin_star_schur, pin_star_start_value,
-            pin_generated_invariants, pin_invalid_input, pin_evaluate_hand,
+            pin_star_order_golden, pin_star_order_relabels, pin_generated_invariants, pin_invalid_input, pin_evaluate_hand,
             pin_evaluate_dense, pin_exact_filter, pin_bin_density, pin_import_csr]
 
 # the eigenvector-placement oracle is numpy (oracle/eigen.py); its pins take

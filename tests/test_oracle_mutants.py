@@ -34,6 +34,9 @@ MUTANTS = {
     "import_degree_skips_first": ("  for (int64_t r = 0; r < num_rows; ++r) {\n    double d = 0.0;\n    for (int64_t p = g->row_ptr[r]; p",
                                   "  for (int64_t r = 0; r < num_rows; ++r) {\n    double d = 0.0;\n    for (int64_t p = g->row_ptr[r] + 1; p"),
     "import_accepts_diagonal": ("col[p] >= num_rows || col[p] == r)", "col[p] >= num_rows)"),
+    "star_order_lower_median": ("? g->ucell[a + m / 2] : 0", "? g->ucell[a + (m - 1) / 2] : 0"),
+    "star_order_labels_ignore_rank": ("int32_t vid = (int32_t)(num_cells + vrank[e]);",
+                                      "int32_t vid = (int32_t)(num_cells + vrank[e] / 2);"),
     "overflow_counts_deficits": ("if (e > 0.0) s = s + e;", "s = s + e;"),
     "overflow_bin_area_unsquared": ("double area = ((xh - xl) / (double)nbx) * ((yh - yl) / (double)nby);",
                                     "double area = (xh - xl) / (double)nbx;"),
