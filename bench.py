@@ -540,7 +540,7 @@ def oracle_worker(argv):
     print("ready", flush=True)
     sys.stdin.readline()
     t0 = time.perf_counter()
-    og = O.build_netlist(nl, star_threshold=STAR)
+    og = O.build_netlist(nl, star_threshold=STAR, star_order="median")
     t1 = time.perf_counter()
     og.filter(x, *EQ5, fixed=nl.fixed)
     t2 = time.perf_counter()
@@ -811,7 +811,7 @@ def main():
         model, ncpu, usable = host_cpu()
         xo = x_host.astype(np.float32).astype(np.float64)
         t0 = time.perf_counter()
-        og = O.build_netlist(nl, star_threshold=STAR)
+        og = O.build_netlist(nl, star_threshold=STAR, star_order="median")
         t1 = time.perf_counter()
         ref = og.filter(xo, *terms, fixed=nl.fixed)
         t2 = time.perf_counter()

@@ -91,9 +91,12 @@ typedef struct gift_graph gift_graph;
  *                   cells with weight M*w(M) (the Laplacian of the star with
  *                   the virtual node eliminated is exactly the clique's).
  *                   T = 0 expands every net as a clique.  Virtual nodes are
- *                   rows N..N+V-1 in ascending net order; they are internal
- *                   and never appear in a signal handed to or returned by the
- *                   library.
+ *                   rows N..N+V-1 in ascending order of their net's median
+ *                   cell (the distinct cell at index M/2 of the net's
+ *                   ascending list), ties in ascending net id, so that
+ *                   neighbouring virtual rows join neighbouring cells; they
+ *                   are internal and never appear in a signal handed to or
+ *                   returned by the library.
  *   storage         gift_dtype of the normalised off-diagonal values and of
  *                   the filter's internal signal iterates.  F32, BF16 and F16
  *                   accumulate in float32; F64 accumulates in float64.

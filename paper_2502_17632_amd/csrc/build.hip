@@ -20,7 +20,9 @@
 //      per distinct (net, cell), whose old value is the slice of that cell's
 //      entries from this net within the row (arbitrary order of the slices;
 //      the atomics overlap the LDS work of the net tiles)
-//   2. per net: clique or star, virtual id, weight
+//   2. per net: clique or star, weight; the star nets' virtual rows in
+//      ascending order of their median cell (then net id), by bucketing on
+//      the median and sorting each bucket in one block
 //   3. exclusive scan of the row counts -> row slices and row tiles (side
 //      stream, beside step 2); emit each pin's (col, net) keys into its slice
 //   4. per row tile, in LDS: sort each row's keys by (col, net) (rank among
@@ -328,8 +330,8 @@ __global__ __launch_bounds__(kBlock) void k_net_tiles(NetArgs a) {
 // 2. classify nets
 // ---------------------------------------------------------------------------
 // Per net: star or clique, weight, the star code (star ? 1 | M << 32 : 0;
-// its exclusive scan gives every star net its virtual row and the number of
-// star entries before it); and the largest net size of the block into
+// its exclusive scan gives every star net its rank among the star nets in
+// net order and the number of star entries before it); and the largest net size of the block into
 // bmax[blockIdx.x] (one atomic max per block on a single word would
 // serialise thousands of blocks at the memory side).
 __global__ __launch_bounds__(kBlock) void k_classify(const int32_t *M, int64_t E, int64_t T,
@@ -377,10 +379,58 @@ __global__ __launch_bounds__(kBlock) void k_max_reduce(const int32_t *v, int64_t
   if (threadIdx.x == 0) *out = red[0];
 }
 
-__global__ void k_virtual_map(const int32_t *is_star, const int64_t *vscan, int64_t E,
-                              int32_t *virt_net) {
-  int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e < E && is_star[e]) virt_net[virtual_rank(vscan, e)] = static_cast<int32_t>(e);
+// ---------------------------------------------------------------------------
+// 2b. labels of the virtual rows: row N + v for the v-th star net in
+//     ascending order of (median cell, net id), the median being the
+//     distinct cell at index M/2 of the net's ascending list.  Neighbouring
+//     virtual rows then gather from neighbouring cells, and a filter pass's
+//     tiles of virtual rows read a few lines of the signal instead of lines
+//     from all over it.  Star nets are bucketed by median (2^kStarShift
+//     cells per bucket) and every bucket is sorted by one block.
+// ---------------------------------------------------------------------------
+constexpr int kStarShift = 12;
+constexpr int kStarScatterBlocks = 256;
+
+// skey[s] = (median << 32 | e) for the s-th star net e in net order; counts
+// per bucket.
+__global__ void k_star_keys(const int32_t *is_star, const int64_t *vscan,
+                            const int64_t *net_ptr, const int32_t *M, const int32_t *ucell,
+                            int64_t E, uint64_t *skey, int32_t *bcnt) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= E || !is_star[e]) return;
+  const int32_t med = ucell[net_ptr[e] + M[e] / 2];
+  skey[virtual_rank(vscan, e)] = (static_cast<uint64_t>(med) << 32) | static_cast<uint32_t>(e);
+  atomicAdd(bcnt + (med >> kStarShift), 1);
+}
+
+// The keys into their buckets' ranges (in any order within a bucket).
+__global__ void k_star_scatter(const uint64_t *skey, const int64_t *vscan, int64_t E,
+                               const int64_t *boff, int32_t *bfill, uint64_t *bkey) {
+  const int64_t V = virtual_rank(vscan, E);
+  for (int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; s < V;
+       s += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const uint64_t k = skey[s];
+    const int64_t b = static_cast<int64_t>(k >> (32 + kStarShift));
+    bkey[boff[b] + atomicAdd(bfill + b, 1)] = k;
+  }
+}
+
+// Block b sorts bucket b (keys are distinct, so the order is unique) and
+// labels its nets: virt_net[v] = e and vrow[e] = v.
+__global__ __launch_bounds__(kBlock) void k_star_sort(uint64_t *bkey, uint64_t *btmp,
+                                                      const int64_t *boff, int32_t *virt_net,
+                                                      int32_t *vrow) {
+  __shared__ uint64_t lds[kChunk64];
+  const int64_t lo = boff[blockIdx.x], n = boff[blockIdx.x + 1] - lo;
+  if (n == 0) return;
+  const bool in_tmp =
+      block_merge_sort_global<uint64_t, kChunk64>(bkey + lo, btmp + lo, n, lds, ~0ull);
+  const uint64_t *sorted = (in_tmp ? btmp : bkey) + lo;
+  for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+    const int32_t e = static_cast<int32_t>(sorted[i] & 0xffffffffu);
+    virt_net[lo + i] = e;
+    vrow[e] = static_cast<int32_t>(lo + i);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -389,7 +439,7 @@ __global__ void k_virtual_map(const int32_t *is_star, const int64_t *vscan, int6
 struct EmitArgs {
   const int64_t *net_ptr;
   const int32_t *ucell, *pin_net, *M, *is_star;
-  const int64_t *vscan;  // scanned star codes
+  const int32_t *vrow;  // virtual row label of each star net
   int64_t E, P, N;
   KeyLayout L;
 };
@@ -419,7 +469,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(EmitArgs a, const int32_t *zoff
       const bool star = a.is_star[e] != 0;
       n = star ? 1 : static_cast<int32_t>(m - 1);
       dst[threadIdx.x] = static_cast<int64_t>(zoff[a.ucell[p]]) + slot[p];
-      lo_of[threadIdx.x] = star ? a.N + virtual_rank(a.vscan, e) : lo;
+      lo_of[threadIdx.x] = star ? a.N + a.vrow[e] : lo;
       net_of[threadIdx.x] = e;
       self_of[threadIdx.x] = star ? -1 : static_cast<int32_t>(i);
       m_of[threadIdx.x] = static_cast<int32_t>(m);
@@ -1005,15 +1055,19 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
                      (long long)(N + E));
 
   // one zeroed block: the error flags (the low word of a 64-bit word, read
-  // back as int64), the largest net size and the row counts (N + 1 int32)
+  // back as int64), the largest net size, the row counts (N + 1 int32) and
+  // the star buckets' counts and fill levels (NB int32 each)
+  const int64_t NB = (N >> kStarShift) + 1;
   int64_t *zero_blk = nullptr;
-  const int64_t zero_words = 2 + (N + 2) / 2;
-  GIFT_TRY(sc.get(&zero_blk, zero_words, "flags, largest net, row counts"));
+  const int64_t zero_words = 2 + (N + 2) / 2 + NB;
+  GIFT_TRY(sc.get(&zero_blk, zero_words, "flags, largest net, row counts, star buckets"));
   GIFT_HIP(hipMemsetAsync(zero_blk, 0, zero_words * 8, st));
   int64_t *flag64 = zero_blk;
   uint32_t *flag = reinterpret_cast<uint32_t *>(flag64);
   int64_t *mmax = zero_blk + 1;
   int32_t *cnt = reinterpret_cast<int32_t *>(zero_blk + 2);
+  int32_t *bcnt = reinterpret_cast<int32_t *>(zero_blk + 2 + (N + 2) / 2);
+  int32_t *bfill = bcnt + NB;
 
   // 0. check net_ptr and tile the nets, then read the flag, the pin count
   //    and the tile count back together; nothing reads pins before the check
@@ -1096,8 +1150,24 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
   k_max_reduce<<<1, kBlock, 0, st>>>(bmax, grid_for(E), mmax);
   GIFT_TRY(check_launch("k_max_reduce"));
   GIFT_TRY(scan_i64(star_code, vscan, E, st));
-  k_virtual_map<<<grid_for(E), kBlock, 0, st>>>(is_star, vscan, E, virt_net);
-  GIFT_TRY(check_launch("k_virtual_map"));
+
+  // 2b. virtual row labels (the star codes are consumed by the scan: their
+  //     block holds the keys)
+  int32_t *vrow = nullptr;
+  int64_t *boff = nullptr;
+  uint64_t *bkey = nullptr, *btmp = nullptr;
+  uint64_t *skey = reinterpret_cast<uint64_t *>(star_code);
+  GIFT_TRY(sc.get(&vrow, E, "virtual row of each star net"));
+  GIFT_TRY(sc.get(&boff, NB + 1, "star bucket offsets"));
+  GIFT_TRY(sc.get(&bkey, E, "star keys by bucket"));
+  GIFT_TRY(sc.get(&btmp, E, "star key sort scratch"));
+  k_star_keys<<<grid_for(E), kBlock, 0, st>>>(is_star, vscan, net_ptr, M, ucell, E, skey, bcnt);
+  GIFT_TRY(check_launch("k_star_keys"));
+  GIFT_TRY(scan_i32_to_i64(bcnt, boff, NB, st));
+  k_star_scatter<<<kStarScatterBlocks, kBlock, 0, st>>>(skey, vscan, E, boff, bfill, bkey);
+  GIFT_TRY(check_launch("k_star_scatter"));
+  k_star_sort<<<static_cast<unsigned>(NB), kBlock, 0, st>>>(bkey, btmp, boff, virt_net, vrow);
+  GIFT_TRY(check_launch("k_star_sort"));
 
   // join: this stream waits for the row offsets and row tiles
   if (hipEventRecord(side.s.done, side.s.stream) != hipSuccess ||
@@ -1105,7 +1175,7 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
     (void)hipGetLastError();
     return set_error(GIFT_EDEVICE, "side stream ordering failed");
   }
-  EmitArgs ea{net_ptr, ucell, pin_net, M, is_star, vscan, E, P, N, KeyLayout{}};
+  EmitArgs ea{net_ptr, ucell, pin_net, M, is_star, vrow, E, P, N, KeyLayout{}};
 
   // sizes back to the host: flag, {V, star entries}, Z, row tiles, largest
   // net

@@ -98,7 +98,7 @@ def run_pair(netlist, x: np.ndarray, terms, *, storage: str = "f32", star_thresh
     if og is None:
         og = O.build_graph(netlist.num_cells, netlist.net_ptr, netlist.pin_cell,
                            weight_model=WEIGHT_MODEL[weight_model],
-                           star_threshold=star_threshold)
+                           star_threshold=star_threshold, star_order="median")
     if structure:
         check_structure(g, og)
     in_dt = torch.float64 if storage == "f64" else torch.float32

@@ -31,7 +31,7 @@ def designs():
 @pytest.fixture(scope="module")
 def oracles(designs):
     nls, _ = designs
-    return [O.build_netlist(nl, star_threshold=16) for nl in nls]
+    return [O.build_netlist(nl, star_threshold=16, star_order="median") for nl in nls]
 
 
 def build_all(nls, storage, sigmas):
@@ -178,7 +178,7 @@ def test_batch_with_empty_and_netless_designs():
     torch.cuda.synchronize()
     assert ys[0].shape == (0, 3)
     for i in (1, 2):
-        og = O.build_netlist(nls[i], star_threshold=16)
+        og = O.build_netlist(nls[i], star_threshold=16, star_order="median")
         ref = og.filter(xs[i], *EQ4)
         assert_close(ys[i].cpu().numpy(), ref, "f64", f"batch degenerate design {i}")
     b.close()

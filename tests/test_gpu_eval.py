@@ -28,7 +28,7 @@ def test_metrics_match_the_oracle_before_and_after_filtering(dtype):
     tdt = torch.float32 if dtype == "f32" else torch.float64
     if dtype == "f32":
         x = x.astype(np.float32).astype(np.float64)
-    og = O.build_netlist(nl, star_threshold=16)
+    og = O.build_netlist(nl, star_threshold=16, star_order="median")
     g = gift.build_graph(nl.num_cells, nl.net_ptr, nl.pin_cell, star_threshold=16,
                          sigmas=[4.0])
     xt = torch.tensor(x, dtype=tdt, device="cuda")
@@ -105,7 +105,7 @@ def test_metrics_with_a_ragged_column_count(threshold):
     import paper_2502_17632_amd as gift
     nl = W.sized(30_000, seed=21)
     x = np.random.default_rng(21).normal(scale=50.0, size=(nl.num_cells, 7))
-    og = O.build_netlist(nl, star_threshold=threshold)
+    og = O.build_netlist(nl, star_threshold=threshold, star_order="median")
     g = gift.build_graph(nl.num_cells, nl.net_ptr, nl.pin_cell, star_threshold=threshold)
     xt = torch.tensor(x, dtype=torch.float64, device="cuda")
     m = gift.evaluate_placement(g, xt, nl.net_ptr, nl.pin_cell)

@@ -17,7 +17,7 @@ def test_exact_filter_matches_the_oracle(storage, tol, bar):
     import paper_2502_17632_amd as gift
     nl = W.medium(seed=5)
     x = W.make_signal(nl, (10.0,), seed=5)
-    og = O.build_netlist(nl, star_threshold=16)
+    og = O.build_netlist(nl, star_threshold=16, star_order="median")
     g = gift.build_graph(nl.num_cells, nl.net_ptr, nl.pin_cell, star_threshold=16,
                          storage=storage, sigmas=[2.0])
     dt = torch.float32 if storage == "f32" else torch.float64

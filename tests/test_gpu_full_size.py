@@ -54,7 +54,7 @@ def test_batched_workload_at_full_size(batch_designs, storage):
         assert max(diffs) == 0.0
     assert max(diffs) <= TOL[storage]
     for i in range(0, len(nls), 8):
-        og = O.build_netlist(nls[i], star_threshold=16)
+        og = O.build_netlist(nls[i], star_threshold=16, star_order="median")
         xin = xs[i].astype(np.float32).astype(np.float64)
         ref = og.filter(xin, *EQ4, fixed=nls[i].fixed)
         og.close()
@@ -104,7 +104,7 @@ def test_serving_pool_at_full_size():
         assert built == (len(nls) if rnd == "cold" else 0)
     srv.close()
     big = int(np.argmax(sizes))
-    og = O.build_netlist(nls[big], star_threshold=16)
+    og = O.build_netlist(nls[big], star_threshold=16, star_order="median")
     ref = og.filter(xs[big].astype(np.float32).astype(np.float64), *EQ4, fixed=nls[big].fixed)
     og.close()
     assert_close(alone[big].double().cpu().numpy(), ref, "f32",

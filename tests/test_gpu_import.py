@@ -50,7 +50,7 @@ def random_weighted(rng, n, density):
 def test_medium_csr_host(storage):
     import paper_2502_17632_amd as gift
     nl = W.medium()
-    ob = O.build_netlist(nl, star_threshold=0)
+    ob = O.build_netlist(nl, star_threshold=0, star_order="median")
     og = O.import_csr(ob.row_ptr, ob.col, ob.w)
     ob.close()
     log(f"[import] medium clique CSR R={og.num_rows} nnz={og.nnz} storage={storage}")

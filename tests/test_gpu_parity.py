@@ -28,7 +28,7 @@ def medium():
 
 @pytest.fixture(scope="module")
 def medium_oracle(medium):
-    return O.build_netlist(medium, star_threshold=16)
+    return O.build_netlist(medium, star_threshold=16, star_order="median")
 
 
 def test_tiny_f64_equal_weights():
@@ -70,7 +70,8 @@ def test_centred_16bit_on_the_fixed_point(storage):
     # nets of at most 16 cells: no star rows, whose start value (the mean of
     # their cells) is not k v
     nl = W.make_netlist(50_000, 500, 55_000, cap=16, seed=7, name="capped")
-    og = O.build_graph(nl.num_cells, nl.net_ptr, nl.pin_cell, star_threshold=16)
+    og = O.build_graph(nl.num_cells, nl.net_ptr, nl.pin_cell, star_threshold=16,
+                       star_order="median")
     assert og.num_virtual == 0
     v = np.sqrt(og.deg + 4.0)
     x = np.stack([3.5 * v, 120.0 * v], axis=1)
@@ -218,7 +219,7 @@ def test_column_counts_and_leading_dimension(cols):
     nl = W.sized(30_000, seed=77)
     rng = np.random.default_rng(cols)
     x = rng.normal(500, 20, size=(nl.num_cells, cols)).astype(np.float32)
-    og = O.build_netlist(nl, star_threshold=16)
+    og = O.build_netlist(nl, star_threshold=16, star_order="median")
     g = gift.build_graph(nl.num_cells, nl.net_ptr, nl.pin_cell, star_threshold=16,
                          sigmas=[2.0, 4.0])
     wide = torch.zeros((nl.num_cells, cols + 5), dtype=torch.float32, device="cuda")
@@ -252,7 +253,7 @@ def test_device_resident_netlist_and_determinism():
     g1 = gift.build_graph(nl.num_cells, npd, pcd, star_threshold=16, sigmas=[4.0])
     g2 = gift.build_graph(nl.num_cells, nl.net_ptr, nl.pin_cell, star_threshold=16,
                           sigmas=[4.0])
-    og = O.build_netlist(nl, star_threshold=16)
+    og = O.build_netlist(nl, star_threshold=16, star_order="median")
     check_structure(g1, og)
     for a, b in zip(g1.export(), g2.export()):
         assert np.array_equal(a, b)
@@ -302,7 +303,7 @@ def test_large_full_size(storage):
     og = getattr(test_large_full_size, "_og", None)
     if og is None:
         log("[parity] building the large oracle graph")
-        og = O.build_netlist(nl, star_threshold=16)
+        og = O.build_netlist(nl, star_threshold=16, star_order="median")
         test_large_full_size._og = og
     y, ref, g, og = run_pair(nl, x, EQ5, storage=storage, star_threshold=16, og=og,
                              fixed=nl.fixed, label=f"large {storage}")

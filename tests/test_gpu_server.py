@@ -87,7 +87,7 @@ def test_results_match_the_oracle(pool):
         srv.wait(t)
         b = big.cpu().numpy()
         assert np.all(b[:, :2] == -3.0) and np.all(b[:, 4] == -3.0)
-        og = O.build_netlist(nls[i], star_threshold=16)
+        og = O.build_netlist(nls[i], star_threshold=16, star_order="median")
         ref = og.filter(xs[i], *EQ4, fixed=nls[i].fixed if i == 2 else None)
         assert_close(b[:, 2:4].astype(np.float64), ref, "f32", f"server design {i}")
     srv.close()
