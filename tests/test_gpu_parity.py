@@ -187,6 +187,39 @@ def test_sort_tiers_and_long_rows():
         assert_close(y, ref, "f32", f"tiers T={thr}")
 
 
+def test_virtual_rows_labelled_by_median():
+    """Virtual rows in ascending (median cell, net id) order, against the
+    oracle's median labelling bit for bit: 3000 star nets whose middle cell is
+    cell 100 (one median bucket of 3000 keys, sorted through global memory
+    since it exceeds one LDS chunk), 300 with medians spread over the design
+    in descending net order, and 200 tied pairs of identical nets."""
+    rng = np.random.default_rng(23)
+    n = 3000 * 8 + 20_000
+    nets = []
+    for e in range(3000):  # 8 cells below 100, cell 100, 8 above: median 100
+        low = [int(c) for c in rng.choice(100, size=8, replace=False)]
+        nets.append(low + [100] + list(range(200 + 8 * e, 208 + 8 * e)))
+    for k in range(300):  # 20-cell nets around a descending anchor
+        a = n - 100 - 60 * k
+        nets.append([a + int(d) for d in rng.choice(np.arange(-40, 40), size=20, replace=False)])
+    for k in range(200):  # identical pairs: equal medians, ordered by net id
+        cells = [int(c) for c in rng.choice(n, size=18, replace=False)]
+        nets += [cells, cells[::-1]]
+    for _ in range(2000):
+        nets.append([int(c) for c in rng.choice(n, size=3, replace=False)])
+    order = rng.permutation(len(nets))
+    nl = handmade([nets[i] for i in order], n)
+    x = rng.normal(500, 50, size=(n, 2))
+    y, ref, g, og = run_pair(nl, x, PAPER, storage="f32", star_threshold=16,
+                             label="median labelling")
+    v = og.num_virtual
+    assert v == 3000 + 300 + 400
+    lens = np.diff(og.row_ptr[n:])
+    med = og.col[og.row_ptr[n:-1] + lens // 2].astype(np.int64)
+    assert np.all(np.diff(med * (1 << 32) + og.virt_net) > 0)
+    assert_close(y, ref, "f32", "median labelling")
+
+
 def test_degenerate_netlists():
     rng = np.random.default_rng(12)
     x = rng.normal(0, 3, size=(6, 2))
