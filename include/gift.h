@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define GIFT_ABI_VERSION 2
+#define GIFT_ABI_VERSION 3
 
 typedef enum {
   GIFT_OK = 0,
@@ -104,6 +104,14 @@ typedef struct gift_graph gift_graph;
  *   sigmas          host double[num_sigmas], each >= 0: the sigma values the
  *                   filter may use.  More can be added with
  *                   gift_graph_add_sigma.
+ *   num_pins        the number of entries of pin_cell, or -1.  The pin count
+ *                   is net_ptr[num_nets]; when num_pins >= 0 the call fails
+ *                   with GIFT_EINVAL unless the two agree, before anything
+ *                   reads a pin.  For a device netlist the library reads
+ *                   net_ptr[num_nets] back itself, so the caller need not
+ *                   (and need not wait for the stream to do so).  -1: the
+ *                   caller vouches that pin_cell holds net_ptr[num_nets]
+ *                   entries.
  *
  * Netlist semantics: repeated pins of one net count once; a net with fewer
  * than two distinct cells adds nothing; weights of different nets on the same
@@ -120,6 +128,7 @@ typedef struct {
   int32_t storage;
   int32_t num_sigmas;
   const double *sigmas;
+  int64_t num_pins;
 } gift_graph_desc;
 
 /* One filter term alpha * A~_sigma^order (Section 3.2.1, eq. proposed_filter).

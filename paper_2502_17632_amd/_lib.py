@@ -30,6 +30,7 @@ class GraphDesc(C.Structure):
         ("storage", C.c_int32),
         ("num_sigmas", C.c_int32),
         ("sigmas", C.c_void_p),
+        ("num_pins", C.c_int64),
     ]
 
 

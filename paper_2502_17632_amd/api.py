@@ -129,7 +129,10 @@ def build_graph(num_cells: int, net_ptr, pin_cell, *, weight_model: str = "inv_m
         raise ValueError("net_ptr must be one-dimensional")
     if net_ptr.shape[0] < 1:
         raise ValueError("net_ptr needs num_nets + 1 >= 1 entries")
-    if int(net_ptr[-1]) != int(pin_cell.shape[0]):
+    # a host netlist's pin count is checked here; a device netlist's by the
+    # library, which reads net_ptr[-1] back anyway (reading it here would
+    # wait for the stream)
+    if mem == L.GIFT_MEM_HOST and int(net_ptr[-1]) != int(pin_cell.shape[0]):
         raise ValueError(f"pin_cell has {int(pin_cell.shape[0])} entries but net_ptr[-1] = "
                          f"{int(net_ptr[-1])}")
     sig = np.ascontiguousarray(list(sigmas), dtype=np.float64)
@@ -144,6 +147,7 @@ def build_graph(num_cells: int, net_ptr, pin_cell, *, weight_model: str = "inv_m
     d.storage = DTYPES[storage]
     d.num_sigmas = int(sig.shape[0])
     d.sigmas = _ptr(sig)
+    d.num_pins = int(pin_cell.shape[0])
     h = C.c_void_p()
     st = _stream_handle(stream)
     L.check(L.lib().gift_build_graph(C.byref(d), st, C.byref(h)), "gift_build_graph")

@@ -1086,7 +1086,12 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
   }
   if (h0[0] & kFlagBadNetPtr)
     return set_error(GIFT_EINVAL, "net_ptr must start at 0, end at the pin count and not decrease");
-  if (d->mem_space != GIFT_MEM_HOST) P = h0[1];
+  if (d->mem_space != GIFT_MEM_HOST) {
+    P = h0[1];
+    if (d->num_pins >= 0 && P != d->num_pins)
+      return set_error(GIFT_EINVAL, "pin_cell has %lld entries but net_ptr[num_nets] = %lld",
+                       (long long)d->num_pins, (long long)P);
+  }
   const int64_t num_net_tiles = h0[2];
   if (P >= (int64_t(1) << 31))
     return set_error(GIFT_EUNSUPPORTED, "netlist too large (pins %lld)", (long long)P);
@@ -1320,8 +1325,12 @@ extern "C" gift_status gift_build_graph(const gift_graph_desc *d, void *stream,
   for (int32_t i = 0; i < d->num_sigmas; ++i)
     if (!(d->sigmas[i] >= 0.0) || !std::isfinite(d->sigmas[i]))
       return set_error(GIFT_EINVAL, "sigma[%d] = %g is not a finite value >= 0", i, d->sigmas[i]);
+  if (d->num_pins < -1) return set_error(GIFT_EINVAL, "num_pins must be >= -1");
   if (d->mem_space == GIFT_MEM_HOST) {
     if (d->net_ptr[0] != 0) return set_error(GIFT_EINVAL, "net_ptr[0] must be 0");
+    if (d->num_pins >= 0 && d->net_ptr[d->num_nets] != d->num_pins)
+      return set_error(GIFT_EINVAL, "pin_cell has %lld entries but net_ptr[num_nets] = %lld",
+                       (long long)d->num_pins, (long long)d->net_ptr[d->num_nets]);
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
   gift_graph *g = new (std::nothrow) gift_graph();

@@ -398,7 +398,7 @@ void builder_main(gift_server *s, int idx) {
       if (std::find(sig.begin(), sig.end(), tm.sigma) == sig.end()) sig.push_back(tm.sigma);
     gift_graph_desc d{req.num_cells, req.num_nets, req.net_ptr, req.pin_cell, GIFT_MEM_HOST,
                       s->cfg.weight_model, s->cfg.star_threshold, s->cfg.storage,
-                      static_cast<int32_t>(sig.size()), sig.data()};
+                      static_cast<int32_t>(sig.size()), sig.data(), -1};
     gift_graph *g = nullptr;
     gift_status status = gift_build_graph(&d, s->build_streams[idx], &g);
     // the build's last kernels may still run on the builder's stream; the

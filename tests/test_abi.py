@@ -37,7 +37,7 @@ def test_every_declared_symbol_has_a_binding_signature():
 
 def test_abi_version_and_status_strings():
     lib = L.lib()
-    assert lib.gift_abi_version() == 2
+    assert lib.gift_abi_version() == 3
     for s in range(6):
         assert lib.gift_status_string(s).startswith(b"GIFT_")
     assert b"unknown" in lib.gift_status_string(99)
@@ -102,7 +102,8 @@ def test_bad_descriptor_fields(field, value):
     sig = np.array([4.0])
     d = L.GraphDesc(num_cells=2, num_nets=1, net_ptr=net_ptr.ctypes.data,
                     pin_cell=pins.ctypes.data, mem_space=L.GIFT_MEM_HOST, weight_model=0,
-                    star_threshold=0, storage=0, num_sigmas=1, sigmas=sig.ctypes.data)
+                    star_threshold=0, storage=0, num_sigmas=1, sigmas=sig.ctypes.data,
+                    num_pins=2)
     setattr(d, field, value)
     out = C.c_void_p()
     assert lib.gift_build_graph(C.byref(d), None, C.byref(out)) == L.GIFT_EINVAL
@@ -118,7 +119,8 @@ def test_negative_sigma_rejected_before_device_work():
         sig = np.array([bad])
         d = L.GraphDesc(num_cells=2, num_nets=1, net_ptr=net_ptr.ctypes.data,
                         pin_cell=pins.ctypes.data, mem_space=L.GIFT_MEM_HOST, weight_model=0,
-                        star_threshold=0, storage=0, num_sigmas=1, sigmas=sig.ctypes.data)
+                        star_threshold=0, storage=0, num_sigmas=1, sigmas=sig.ctypes.data,
+                    num_pins=2)
         out = C.c_void_p()
         assert lib.gift_build_graph(C.byref(d), None, C.byref(out)) == L.GIFT_EINVAL
 
@@ -131,9 +133,30 @@ def test_host_net_ptr_must_start_at_zero():
     sig = np.array([4.0])
     d = L.GraphDesc(num_cells=2, num_nets=1, net_ptr=net_ptr.ctypes.data,
                     pin_cell=pins.ctypes.data, mem_space=L.GIFT_MEM_HOST, weight_model=0,
-                    star_threshold=0, storage=0, num_sigmas=1, sigmas=sig.ctypes.data)
+                    star_threshold=0, storage=0, num_sigmas=1, sigmas=sig.ctypes.data,
+                    num_pins=2)
     out = C.c_void_p()
     assert lib.gift_build_graph(C.byref(d), None, C.byref(out)) == L.GIFT_EINVAL
+
+
+def test_pin_count_checked_before_device_work():
+    """num_pins: a host netlist whose pin count (net_ptr[num_nets]) differs
+    from the stated length of pin_cell, or a num_pins below -1, is rejected
+    before any device work."""
+    import numpy as np
+    lib = L.lib()
+    net_ptr = np.array([0, 2, 5], dtype=np.int64)
+    pins = np.array([0, 1, 1], dtype=np.int32)
+    sig = np.array([4.0])
+    for num_pins in (3, 4, -2):
+        d = L.GraphDesc(num_cells=3, num_nets=2, net_ptr=net_ptr.ctypes.data,
+                        pin_cell=pins.ctypes.data, mem_space=L.GIFT_MEM_HOST, weight_model=0,
+                        star_threshold=0, storage=0, num_sigmas=1, sigmas=sig.ctypes.data,
+                        num_pins=num_pins)
+        out = C.c_void_p()
+        assert lib.gift_build_graph(C.byref(d), None, C.byref(out)) == L.GIFT_EINVAL
+        assert out.value is None
+        assert b"num_pins" in lib.gift_last_error() or b"entries" in lib.gift_last_error()
 
 
 def test_batch_arguments_rejected_without_device_work():

@@ -316,6 +316,10 @@ def test_invalid_netlists_are_rejected():
             assert ei.value.status == 1
     with pytest.raises(ValueError):  # pin array shorter than net_ptr[-1]
         gift.build_graph(3, np.array([0, 2, 5]), np.array([0, 1, 1]))
+    with pytest.raises(gift.GiftError) as ei:  # the same on the device: the library checks
+        gift.build_graph(3, torch.tensor([0, 2, 5], device="cuda"),
+                         torch.tensor([0, 1, 1], dtype=torch.int32, device="cuda"))
+    assert ei.value.status == 1
     g = gift.build_graph(3, np.array([0, 2]), np.array([0, 1]), sigmas=[4.0])
     x = torch.zeros((3, 2), device="cuda")
     with pytest.raises(gift.GiftError):
