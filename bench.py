@@ -136,6 +136,54 @@ def timed_events(torch, fn, reps, warm=3):
     return e0.elapsed_time(e1) / reps
 
 
+def timed_events_each(torch, fn, reps, warm=3):
+    """Per-call device times (ms) of `reps` back-to-back calls: events
+    between the calls on the current stream, no synchronisation between
+    them."""
+    import numpy as np
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record()
+    for k in range(reps):
+        fn()
+        ev[k + 1].record()
+    torch.cuda.synchronize()
+    return np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(reps)])
+
+
+def host_end_to_end(gift, torch, nl, x_host, terms, reps=5):
+    """One step with the netlist and the signal in host memory and the result
+    copied back to host memory: the build reads the netlist from pageable
+    host arrays (the library uploads it), the signal and the fixed mask go up
+    from pinned buffers, the filtered placement comes back into a pinned
+    buffer.  Wall time per step, synchronised at both ends."""
+    import numpy as np
+    xp = torch.from_numpy(np.ascontiguousarray(x_host, dtype=np.float32)).pin_memory()
+    fp = torch.from_numpy(np.ascontiguousarray(nl.fixed)).pin_memory()
+    out = torch.empty(xp.shape, dtype=torch.float32).pin_memory()
+
+    def once():
+        g = gift.build_graph(nl.num_cells, nl.net_ptr, nl.pin_cell, star_threshold=STAR,
+                             sigmas=[4.0])
+        xd = xp.to("cuda", non_blocking=True)
+        fd = fp.to("cuda", non_blocking=True)
+        y = gift.filter_placement(g, *terms, xd, fixed=fd)
+        out.copy_(y, non_blocking=True)
+        g.close()
+
+    once()
+    torch.cuda.synchronize()
+    t = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        once()
+        torch.cuda.synchronize()
+        t.append((time.perf_counter() - t0) * 1e3)
+    return float(np.median(t)), out.numpy().copy()
+
+
 def attainable_bandwidth(torch):
     """A plain device copy of 1 GiB (read + write): what a streaming kernel
     reaches on this GPU, beside the 8 TB/s peak."""
@@ -729,14 +777,27 @@ def main():
         out["build"]["roofline"] = build_roofline(torch, nl, build_ms, b_bytes,
                                                   out["attainable"]["copy_GBs"])
         # the filter alone on a resident graph
-        ms_f = timed_events(torch, lambda: gift.filter_placement(g, *terms, x, fixed=fixed,
-                                                                 out=y), 20)
+        each = timed_events_each(torch, lambda: gift.filter_placement(g, *terms, x, fixed=fixed,
+                                                                      out=y), 20)
+        ms_f = float(each.mean())
         fbytes = filter_bytes(info["nnz"], info["num_rows"], info["nnz_cells"],
                               info["num_cells"], 2, max(orders), len(orders), args.storage)
         out["filter_only"] = {"ms": round(ms_f, 4), "nnz_cols_per_s": work / (ms_f * 1e-3),
+                              "median_ms": round(float(np.median(each)), 4),
+                              "p10_ms": round(float(np.percentile(each, 10)), 4),
+                              "p90_ms": round(float(np.percentile(each, 90)), 4),
+                              "reps": int(each.size),
                               "algorithmic_bytes": fbytes,
                               "algorithmic_GBs": round(fbytes / (ms_f * 1e-3) / 1e9, 1),
                               "frac": round(fbytes / (ms_f * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        # the same step with host-resident inputs and output (PCIe included)
+        h_ms, y_host = host_end_to_end(gift, torch, nl, x_host, terms)
+        out["host_inputs"] = {
+            "ms_per_step": round(h_ms, 3), "nnz_cols_per_s": work / (h_ms * 1e-3),
+            "equal_to_device_inputs": bool(np.array_equal(y_host, y.cpu().numpy())),
+            "note": "netlist in pageable host arrays (uploaded by the build), signal and "
+                    "fixed mask from pinned host buffers, result copied back to pinned host "
+                    "memory; median wall time of 5 steps"}
         y_f32 = y.double().cpu().numpy()
         # what the filter does to the placement (fixed cells restored):
         # smoothness / quadratic wirelength, Rayleigh quotient and HPWL
