@@ -64,6 +64,10 @@ def host_cpu():
     return model, os.cpu_count(), usable
 
 
+# the timed steps whose launches the library's event profiler brackets
+PROF_EVERY = 5
+
+
 def counter_traffic():
     """HBM bytes per SpMM launch measured with rocprofv3 counters, if they were
     taken on the current kernel source."""
@@ -702,9 +706,14 @@ def main():
     nnz_cells = int(row_ptr[nl.num_cells])
     log("[bench] warmup")
     info = None
+    # the warm-up runs with the event profiler on, so that its event pool is
+    # filled before the timed steps (records collected and dropped below)
+    gift.profile_enable(True)
     for _ in range(args.warmup):
         info = step()
     torch.cuda.synchronize()
+    for kind in ("spmm", "spmm_final", "build"):
+        gift.profile_collect(kind)
     if info is None:
         info = step()
         torch.cuda.synchronize()
@@ -713,12 +722,17 @@ def main():
     log(f"[bench] timing {args.steps} steps")
     gift.profile_enable(True)
     torch.cuda.synchronize()
-    # events between the steps on the stream the steps run on: per-step
-    # times without a synchronisation inside the timed region
+    # The library's events bracket every launch of the steps the profiler
+    # samples (one step in PROF_EVERY, the first one included): the events
+    # cost about 80 us per step, so sampling keeps them off most steps.
+    # Events between the steps on the stream the steps run on give per-step
+    # times without a synchronisation inside the timed region.
     marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    sampled = [k for k in range(args.steps) if k % PROF_EVERY == 0]
     t0 = time.perf_counter()
     marks[0].record()
     for k in range(args.steps):
+        gift.profile_pause(k % PROF_EVERY != 0)
         step()
         marks[k + 1].record()
     torch.cuda.synchronize()
@@ -747,6 +761,7 @@ def main():
         "metric": METRIC, "value": value, "unit": "nnz·cols/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
         "step_ms": step_ms,
+        "profiled_steps": sampled,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.storage, "data": "synthetic",
         "config": {"workload": "large: 2M+20k cells, 2.1M nets, Zipf(2.2) pins <= 1000, "

@@ -695,6 +695,15 @@ typedef enum {
 gift_status gift_profile_enable(int32_t on);
 
 /*
+ * Pause (paused != 0) or resume the enabled profiler without waiting for or
+ * clearing its records: while paused no events are recorded, so launches run
+ * as with the profiler off.  A caller can time a sample of its launches this
+ * way without paying the events on every launch.  Enabling or disabling
+ * resumes.
+ */
+gift_status gift_profile_pause(int32_t paused);
+
+/*
  * Totals since the last enable/collect for one class: number of launches,
  * summed and per-launch maximum device duration (milliseconds, from the
  * event pairs) and the summed algorithmic bytes of the launches.  An SpMM

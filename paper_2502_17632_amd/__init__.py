@@ -10,5 +10,5 @@ does.
 from .api import (Batch, Graph, Server, bin_density, build_graph,  # noqa: F401
                   density_overflow, eigen_placement, evaluate_placement,
                   filter_exact, filter_placement, import_csr, make_terms, profile_collect,
-                  profile_enable, set_allocator, TorchAllocator, use_torch_allocator)
+                  profile_enable, profile_pause, set_allocator, TorchAllocator, use_torch_allocator)
 from ._lib import GiftError, lib  # noqa: F401

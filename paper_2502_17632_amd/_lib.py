@@ -219,6 +219,7 @@ SIGNATURES = {
     "gift_server_get_stats": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(ServerStats)]),
     "gift_server_destroy": (C.c_int, [C.c_void_p]),
     "gift_profile_enable": (C.c_int, [C.c_int32]),
+    "gift_profile_pause": (C.c_int, [C.c_int32]),
     "gift_profile_collect": (C.c_int, [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                        C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "gift_memory_stats": (C.c_int, [C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),

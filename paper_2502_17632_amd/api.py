@@ -625,6 +625,11 @@ def profile_enable(on: bool = True):
     L.check(L.lib().gift_profile_enable(1 if on else 0), "gift_profile_enable")
 
 
+def profile_pause(paused: bool = True):
+    """Pause or resume the enabled profiler, keeping its records."""
+    L.check(L.lib().gift_profile_pause(1 if paused else 0), "gift_profile_pause")
+
+
 def profile_collect(kind: str) -> dict:
     """Launch count, device time and algorithmic bytes recorded for one kernel
     class ("spmm", "spmm_final" or "build") since the last collect."""

@@ -19,6 +19,7 @@ struct Rec {
 struct Profiler {
   std::mutex m;
   bool on = false;
+  bool paused = false;
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
 
@@ -44,7 +45,7 @@ Profiler &prof() {
 ProfScope::ProfScope(hipStream_t s, int cls, double bytes) : idx_(-1), stream_(s) {
   Profiler &p = prof();
   std::lock_guard<std::mutex> lk(p.m);
-  if (!p.on) return;
+  if (!p.on || p.paused) return;
   hipEvent_t a = p.take(), b = p.take();
   if (!a || !b || hipEventRecord(a, s) != hipSuccess) {
     if (a) p.pool.push_back(a);
@@ -66,7 +67,7 @@ bool prof_launch_events(int cls, double bytes, hipEvent_t *start, hipEvent_t *st
   *start = *stop = nullptr;
   Profiler &p = prof();
   std::lock_guard<std::mutex> lk(p.m);
-  if (!p.on) return false;
+  if (!p.on || p.paused) return false;
   hipEvent_t a = p.take(), b = p.take();
   if (!a || !b) {
     if (a) p.pool.push_back(a);
@@ -94,6 +95,15 @@ extern "C" gift_status gift_profile_enable(int32_t on) {
   }
   p.recs.clear();
   p.on = on != 0;
+  p.paused = false;
+  return GIFT_OK;
+}
+
+extern "C" gift_status gift_profile_pause(int32_t paused) {
+  clear_error();
+  Profiler &p = prof();
+  std::lock_guard<std::mutex> lk(p.m);
+  p.paused = paused != 0;
   return GIFT_OK;
 }
 
