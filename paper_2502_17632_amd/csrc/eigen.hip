@@ -222,62 +222,163 @@ __global__ __launch_bounds__(kBlock) void k_eig_star_means(const int32_t *row_pt
 }
 
 // out = alpha (L x) + beta x + gamma prev on the giant component's cells, 0
-// elsewhere (prev may be NULL).  One thread per cell row.
-__global__ __launch_bounds__(kBlock) void k_eig_apply(const int32_t *row_ptr, const int32_t *col,
-                                                      const double *w, const double *deg,
-                                                      const int32_t *label, int32_t giant,
-                                                      int64_t N, const double *x,
-                                                      const double *ext, const double *prev,
-                                                      double alpha, double beta, double gamma,
-                                                      double *out) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  const gptr<const double> xg = to_global(x), eg = to_global(ext);
+// elsewhere (prev may be NULL).  One block per SpMM row tile of cell rows
+// (class 0): the tile's columns and weights are staged in LDS with every
+// load in flight at once, then each row is taken by a group of lanes (one
+// lane when the tile has many rows), four gathers of 32-byte rows in flight
+// per lane, the group's partial sums combined by a fixed shuffle tree.  A
+// row longer than the class's limit has a tile of its own and the whole
+// block: lanes over its entries, then a fixed tree over the block.  The
+// order is the same on every run.
+__device__ __forceinline__ int eig_lanes_for(int rows) {
+  int g = 1;
+  while (g < 64 && rows * g * 2 <= kBlock) g <<= 1;
+  return g;
+}
+
+__device__ __forceinline__ void eig_row_out(int64_t i, const double (&acc)[K], bool in,
+                                            const double *deg, const double *x,
+                                            const double *prev, double alpha, double beta,
+                                            double gamma, double *out) {
   double o[K] = {};
-  if (label[i] == giant) {
-    double acc[K] = {};
-    const gptr<const int32_t> cl = to_global(col);
-    const gptr<const double> wv = to_global(w);
-    const int32_t p0 = row_ptr[i], p1 = row_ptr[i + 1];
-    int32_t p = p0;
-    // four entries at a time, their loads issued before the adds (which keep
-    // the entry order of the plain loop)
-    for (; p + 3 < p1; p += 4) {
-      int64_t j[4];
-      double wj[4], v[4][K];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        j[u] = cl[p + u];
-        wj[u] = wv[p + u];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const gptr<const double> src = j[u] < N ? xg + j[u] * K : eg + (j[u] - N) * K;
-#pragma unroll
-        for (int q = 0; q < K; ++q) v[u][q] = src[q];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int q = 0; q < K; ++q) acc[q] += wj[u] * v[u][q];
-    }
-    for (; p < p1; ++p) {
-      const int64_t j = cl[p];
-      const double wj = wv[p];
-      const gptr<const double> src = j < N ? xg + j * K : eg + (j - N) * K;
-#pragma unroll
-      for (int q = 0; q < K; ++q) acc[q] += wj * src[q];
-    }
-    const double d = deg[i];
+  if (in) {
+    const double d = to_global(deg)[i];
 #pragma unroll
     for (int q = 0; q < K; ++q) {
-      const double xi = xg[i * K + q];
+      const double xi = to_global(x)[i * K + q];
       o[q] = alpha * (d * xi - acc[q]) + beta * xi;
       if (prev) o[q] += gamma * to_global(prev)[i * K + q];
     }
   }
 #pragma unroll
   for (int q = 0; q < K; ++q) out[i * K + q] = o[q];
+}
+
+__global__ __launch_bounds__(kBlock) void k_eig_apply(const TileDesc *tiles,
+                                                      const int32_t *row_ptr, const int32_t *col,
+                                                      const double *w, const double *deg,
+                                                      const int32_t *label, int32_t giant,
+                                                      int64_t N, const double *x,
+                                                      const double *ext, const double *prev,
+                                                      double alpha, double beta, double gamma,
+                                                      double *out) {
+  using TCL = TileClass<0>;
+  constexpr int kStage = (TCL::kCap + kBlock - 1) / kBlock;
+  __shared__ int32_t loff[TCL::kRows + 1];
+  __shared__ int32_t lcol[TCL::kCap];
+  __shared__ double lw[TCL::kCap];
+  __shared__ double red[kBlock / kWave][K];
+  const TileDesc td = gload(tiles, xcd_remap(blockIdx.x, gridDim.x));
+  const gptr<const double> xg = to_global(x), eg = to_global(ext), wg = to_global(w);
+  const gptr<const int32_t> cg = to_global(col), rp = to_global(row_ptr);
+  const int ns = td.r1 - td.r0, n = td.p1 - td.p0;
+  const int tid = threadIdx.x;
+  auto src_of = [&](int64_t j) { return j < N ? xg + j * K : eg + (j - N) * K; };
+  if (ns == 1 && n > TCL::kLong) {
+    const int64_t i = td.r0;
+    const bool in = to_global(label)[i] == giant;
+    double acc[K] = {};
+    if (in) {
+      int q = td.p0 + tid;
+      for (; q + 3 * kBlock < td.p1; q += 4 * kBlock) {
+        int64_t j[4];
+        double wj[4], v[4][K];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          j[u] = cg[q + u * kBlock];
+          wj[u] = wg[q + u * kBlock];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const gptr<const double> src = src_of(j[u]);
+#pragma unroll
+          for (int k = 0; k < K; ++k) v[u][k] = src[k];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int k = 0; k < K; ++k) acc[k] += wj[u] * v[u][k];
+      }
+      for (; q < td.p1; q += kBlock) {
+        const double wj = wg[q];
+        const gptr<const double> src = src_of(cg[q]);
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc[k] += wj * src[k];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      for (int off = kWave / 2; off > 0; off >>= 1) acc[k] += __shfl_xor(acc[k], off);
+      if ((tid & (kWave - 1)) == 0) red[tid / kWave][k] = acc[k];
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double tot[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        tot[k] = red[0][k];
+        for (int wv = 1; wv < kBlock / kWave; ++wv) tot[k] += red[wv][k];
+      }
+      eig_row_out(i, tot, in, deg, x, prev, alpha, beta, gamma, out);
+    }
+    return;
+  }
+  {
+    int32_t cj[kStage];
+    double wv[kStage];
+#pragma unroll
+    for (int k = 0; k < kStage; ++k) {
+      const int i = tid + k * kBlock;
+      const int q = i < n ? td.p0 + i : 0;  // unused slots read entry 0, which always exists
+      cj[k] = cg[q];
+      wv[k] = wg[q];
+    }
+    for (int i = tid; i <= ns; i += kBlock) loff[i] = rp[td.r0 + i] - td.p0;
+#pragma unroll
+    for (int k = 0; k < kStage; ++k) {
+      const int i = tid + k * kBlock;
+      if (i < n) {
+        lcol[i] = cj[k];
+        lw[i] = wv[k];
+      }
+    }
+  }
+  __syncthreads();
+  const int G = eig_lanes_for(ns);
+  const int lane = tid & (G - 1);
+  for (int base = 0; base < ns; base += kBlock / G) {
+    const int rr = base + tid / G;
+    const bool live = rr < ns;
+    const int64_t i = td.r0 + (live ? rr : 0);
+    const bool in = live && to_global(label)[i] == giant;
+    double acc[K] = {};
+    if (in) {
+      const int q1 = loff[rr + 1];
+      int q = loff[rr] + lane;
+      for (; q + 3 * G < q1; q += 4 * G) {
+        double v[4][K];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const gptr<const double> src = src_of(lcol[q + u * G]);
+#pragma unroll
+          for (int k = 0; k < K; ++k) v[u][k] = src[k];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int k = 0; k < K; ++k) acc[k] += lw[q + u * G] * v[u][k];
+      }
+      for (; q < q1; q += G) {
+        const gptr<const double> src = src_of(lcol[q]);
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc[k] += lw[q] * src[k];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      for (int off = G >> 1; off > 0; off >>= 1) acc[k] += __shfl_xor(acc[k], off);
+    if (live && lane == 0) eig_row_out(i, acc, in, deg, x, prev, alpha, beta, gamma, out);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -638,8 +739,12 @@ struct EigenRun {
   gift_status apply(const double *x, const double *prev, double alpha, double beta, double gamma,
                     double *out) {
     GIFT_TRY(star(x));
-    k_eig_apply<<<grid_for(N), kBlock, 0, st>>>(g->row_ptr, g->col, g->w, g->deg, label, giant,
-                                                 N, x, ext, prev, alpha, beta, gamma, out);
+    // the cell tiles of class 0 cover rows 0..N-1 (star rows come after)
+    const int64_t T = g->num_tiles_cells[0];
+    if (T == 0) return GIFT_OK;
+    k_eig_apply<<<static_cast<unsigned>(T), kBlock, 0, st>>>(
+        g->tiles[0], g->row_ptr, g->col, g->w, g->deg, label, giant, N, x, ext, prev, alpha,
+        beta, gamma, out);
     return check_launch("k_eig_apply");
   }
   gift_status gram(const double *a, const double *b) {
