@@ -130,27 +130,38 @@ __device__ __forceinline__ void emit_row(const FinalArgs &f, const GraphDev &gd,
 #pragma unroll
       for (int c = 0; c < C; ++c) s[c] = 0.0;
       const double dl = cen ? to_global(gd.deg)[lr] : 0.0;
-      // every column sums the terms in term order
-      for (int t = 0; t < f.num_terms; ++t) {
-        const T *src = static_cast<const T *>(f.src[t]);
-        double v[C];
-        if (src) {
-          const auto row = load_row<T, C>(src, srow);
+      // every column sums the terms in term order; the saved rows of four
+      // terms are loaded before any of them is added
+      constexpr int kTermBatch = 4;
+      for (int t0 = 0; t0 < f.num_terms; t0 += kTermBatch) {
+        double v[kTermBatch][C];
 #pragma unroll
-          for (int c = 0; c < C; ++c) v[c] = static_cast<double>(S::load(row.v[c]));
-        } else {
+        for (int u = 0; u < kTermBatch; ++u) {
+          const int t = t0 + u;
+          const T *src = t < f.num_terms ? static_cast<const T *>(f.src[t]) : nullptr;
+          if (src) {
+            const auto row = load_row<T, C>(src, srow);
 #pragma unroll
-          for (int c = 0; c < C; ++c) v[c] = static_cast<double>(acc[c]);
+            for (int c = 0; c < C; ++c) v[u][c] = static_cast<double>(S::load(row.v[c]));
+          } else {
+#pragma unroll
+            for (int c = 0; c < C; ++c) v[u][c] = static_cast<double>(acc[c]);
+          }
         }
-        if (cen) {
-          const double vt = sqrt(dl + f.term_sigma[t]);
-          const gptr<const double> ct = to_global(cen) + f.term_group[t] * C;
 #pragma unroll
-          for (int c = 0; c < C; ++c) v[c] = v[c] + ct[c] * vt;
+        for (int u = 0; u < kTermBatch; ++u) {
+          const int t = t0 + u;
+          if (t >= f.num_terms) break;
+          if (cen) {
+            const double vt = sqrt(dl + f.term_sigma[t]);
+            const gptr<const double> ct = to_global(cen) + f.term_group[t] * C;
+#pragma unroll
+            for (int c = 0; c < C; ++c) v[u][c] = v[u][c] + ct[c] * vt;
+          }
+          const double a = f.alpha[t];
+#pragma unroll
+          for (int c = 0; c < C; ++c) s[c] = s[c] + a * v[u][c];
         }
-        const double a = f.alpha[t];
-#pragma unroll
-        for (int c = 0; c < C; ++c) s[c] = s[c] + a * v[c];
       }
     }
 #pragma unroll
