@@ -452,16 +452,43 @@ __global__ __launch_bounds__(kBlock) void k_prep(LaunchArgs l, int32_t in_dtype,
     }
     return;
   }
-  // star rows (more than 16 entries each): a group of at least 16 lanes per
-  // row, more when the tile has few rows
+  // star rows (more than 16 entries each): the tile's columns and row
+  // offsets are staged in LDS first, with all of a thread's loads in flight
+  // at once (a single row too long for the stage reads them in place); then
+  // a group of at least 16 lanes per row, more when the tile has few rows,
+  // gathers the cells' rows four at a time per lane
+  constexpr int kPrepCap = TileClass<0>::kCap;
+  constexpr int kPrepStage = (kPrepCap + kBlock - 1) / kBlock;
+  __shared__ int32_t pcol[kPrepCap];
+  __shared__ int32_t poff[TileClass<0>::kRows + 1];
   const int nrows = td.r1 - td.r0;
+  const int n = td.p1 - td.p0;
+  const bool staged = n <= kPrepCap;
+  if (staged) {
+    int32_t cv[kPrepStage];
+#pragma unroll
+    for (int k = 0; k < kPrepStage; ++k) {
+      const int i = static_cast<int>(threadIdx.x) + k * kBlock;
+      cv[k] = i < n ? col[td.p0 + i] : 0;
+    }
+    for (int i = threadIdx.x; i <= nrows; i += kBlock) poff[i] = row_ptr[td.r0 + i] - td.p0;
+#pragma unroll
+    for (int k = 0; k < kPrepStage; ++k) {
+      const int i = static_cast<int>(threadIdx.x) + k * kBlock;
+      if (i < n) pcol[i] = cv[k];
+    }
+    __syncthreads();
+  }
+  auto col_at = [&](int32_t q) -> int64_t { return staged ? pcol[q] : col[td.p0 + q]; };
   const int G = lanes_for(nrows) > 16 ? lanes_for(nrows) : 16;
   const int lane = threadIdx.x & (G - 1);
   for (int base = 0; base < nrows; base += kBlock / G) {
     const int rr = base + static_cast<int>(threadIdx.x) / G;
     const bool live = rr < nrows;
     const int r = td.r0 + (live ? rr : 0);
-    const int32_t p0 = row_ptr[r], p1 = live ? row_ptr[r + 1] : p0;
+    // entries of the row, local to the tile
+    const int32_t p0 = live ? (staged ? poff[rr] : row_ptr[r] - td.p0) : 0;
+    const int32_t p1 = live ? (staged ? poff[rr + 1] : row_ptr[r + 1] - td.p0) : 0;
     double s[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) s[c] = 0.0;
@@ -470,7 +497,7 @@ __global__ __launch_bounds__(kBlock) void k_prep(LaunchArgs l, int32_t in_dtype,
     for (; q + 3 * G < p1; q += 4 * G) {
       int64_t j[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) j[u] = col[q + u * G];
+      for (int u = 0; u < 4; ++u) j[u] = col_at(q + u * G);
       double xv[4][C];
 #pragma unroll
       for (int u = 0; u < 4; ++u)
@@ -482,7 +509,7 @@ __global__ __launch_bounds__(kBlock) void k_prep(LaunchArgs l, int32_t in_dtype,
         for (int c = 0; c < C; ++c) s[c] += xv[u][c];
     }
     for (; q < p1; q += G) {
-      const int64_t j = col[q];
+      const int64_t j = col_at(q);
 #pragma unroll
       for (int c = 0; c < C; ++c) s[c] += load_in(io.x_in, in_dtype, j * io.ld_in + col0 + c);
     }
