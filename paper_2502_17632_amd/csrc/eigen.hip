@@ -27,8 +27,9 @@
 //      Cholesky QR twice, and takes the Ritz pairs of the 4 x 4 projected
 //      matrix (cyclic Jacobi).  It stops when the residuals of u_2 and u_3
 //      are at most tol * b.
-// Every reduction is formed per block over a fixed row range and summed in
-// block order, so results are deterministic.
+// Every reduction is formed per block over a fixed row range, and the
+// blocks' partial sums are added in a fixed order, so results are
+// deterministic.
 #include <cmath>
 #include <cstring>
 
@@ -382,7 +383,8 @@ __global__ __launch_bounds__(kBlock) void k_eig_apply(const TileDesc *tiles,
 }
 
 // ---------------------------------------------------------------------------
-// block reductions over the N rows (fixed ranges, block order)
+// block reductions over the N rows (fixed ranges; partials added in a fixed
+// order)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void row_range(int64_t n, int64_t *lo, int64_t *hi) {
   const int64_t per = (n + gridDim.x - 1) / gridDim.x;

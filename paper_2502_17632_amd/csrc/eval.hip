@@ -8,8 +8,8 @@
 //            (eq. smoothness_ray);
 //   HPWL   = sum over nets of max - min of g over the net's pins.
 // Everything is float64.  Sums are formed per row tile (S) or per block of
-// nets (HPWL) in a fixed order and the partial sums are added in tile order,
-// so the results are deterministic.
+// nets (HPWL) in a fixed order and the partial sums are added in a fixed
+// order too, so the results are deterministic.
 #include "common.h"
 #include "devutil.h"
 

@@ -870,7 +870,7 @@ size_t chunk_buffer_bytes(const FilterPlan &pl, int C) {
 // on (2 I - A~_sigma) g' = g over all R rows, per column, from g' = 0.  One
 // iteration is an SpMM pass (the same kernel as the filter) and three fused
 // vector kernels; dot products are float64, summed per block over fixed
-// ranges and then in block order (deterministic).  The scalars stay on the
+// ranges and then across blocks in a fixed order (deterministic).  The scalars stay on the
 // device; the host reads the residuals every few iterations to stop.
 // ---------------------------------------------------------------------------
 namespace {
