@@ -329,25 +329,54 @@ __global__ __launch_bounds__(kBlock) void k_net_tiles(NetArgs a) {
 // ---------------------------------------------------------------------------
 // 2. classify nets
 // ---------------------------------------------------------------------------
-// Per net: star or clique, weight, the star code (star ? 1 | M << 32 : 0;
-// its exclusive scan gives every star net its rank among the star nets in
-// net order and the number of star entries before it); and the largest net size of the block into
-// bmax[blockIdx.x] (one atomic max per block on a single word would
-// serialise thousands of blocks at the memory side).
+// Labels of the virtual rows: row N + v for the v-th star net in ascending
+// order of (median cell, net id), the median being the distinct cell at
+// index M/2 of the net's ascending list.  Neighbouring virtual rows then
+// gather from neighbouring cells, and a filter pass's tiles of virtual rows
+// read a few lines of the signal instead of lines from all over it.  The
+// classification writes each star net's key and counts it in its median
+// bucket (2^kStarShift cells per bucket); the keys are then placed in their
+// buckets and every bucket is sorted by one block (step 2b).
+constexpr int kStarShift = 12;
+
+struct StarKeys {
+  const int64_t *net_ptr;
+  const int32_t *ucell;
+  uint64_t *key;  // per net: (median << 32 | e), star nets only
+  int32_t *bcnt;  // star nets per median bucket (zeroed before)
+};
+
+__device__ __forceinline__ void star_key(const StarKeys &sk, int64_t e, int64_t m) {
+  const int32_t med = sk.ucell[sk.net_ptr[e] + m / 2];
+  sk.key[e] = (static_cast<uint64_t>(med) << 32) | static_cast<uint32_t>(e);
+  atomicAdd(sk.bcnt + (med >> kStarShift), 1);
+}
+
+// Per net: star or clique and weight, the star net's label key (above); per
+// block the largest net size into bmax[blockIdx.x] and the star nets' cells
+// (the star rows' entries) into bstar[blockIdx.x] (one atomic per block on a
+// single word would serialise thousands of blocks at the memory side).
 __global__ __launch_bounds__(kBlock) void k_classify(const int32_t *M, int64_t E, int64_t T,
                                                      int model, int32_t *is_star, double *wnet,
-                                                     int64_t *star_code, int32_t *bmax) {
+                                                     int32_t *bmax, int64_t *bstar,
+                                                     StarKeys sk) {
   __shared__ int32_t red[kBlock];
+  __shared__ int64_t tmp[kBlock / kWave];
   int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   int32_t mine = 0;
+  int64_t star_m = 0;
   if (e < E) {
     int64_t m = M[e];
     bool star = m >= 2 && T > 0 && m > T;
     is_star[e] = star ? 1 : 0;
-    star_code[e] = star ? (1 | (m << 32)) : 0;
     wnet[e] = m < 2 ? 0.0 : (star ? star_weight(m, model) : clique_weight(m, model));
     mine = static_cast<int32_t>(m);
+    if (star) {
+      star_key(sk, e, m);
+      star_m = m;
+    }
   }
+  const int64_t stars = block_sum<int64_t>(star_m, tmp);
   red[threadIdx.x] = mine;
   __syncthreads();
   for (int off = kBlock / 2; off > 0; off >>= 1) {
@@ -355,20 +384,24 @@ __global__ __launch_bounds__(kBlock) void k_classify(const int32_t *M, int64_t E
       red[threadIdx.x] = red[threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x == 0) bmax[blockIdx.x] = red[0];
+  if (threadIdx.x == 0) {
+    bmax[blockIdx.x] = red[0];
+    bstar[blockIdx.x] = stars;
+  }
 }
 
-// Virtual row of star net e from the scanned star codes.
-__device__ __forceinline__ int64_t virtual_rank(const int64_t *vscan, int64_t e) {
-  return vscan[e] & 0xffffffff;
-}
-
-// *out = max of v[0..n), one block.
-__global__ __launch_bounds__(kBlock) void k_max_reduce(const int32_t *v, int64_t n,
-                                                       int64_t *out) {
+// out[0] = max of v[0..n), out[1] = sum of w[0..n), one block.
+__global__ __launch_bounds__(kBlock) void k_max_reduce(const int32_t *v, const int64_t *w,
+                                                       int64_t n, int64_t *out) {
   __shared__ int32_t red[kBlock];
+  __shared__ int64_t tmp[kBlock / kWave];
   int32_t m = 0;
-  for (int64_t i = threadIdx.x; i < n; i += kBlock) m = v[i] > m ? v[i] : m;
+  int64_t sum = 0;
+  for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+    m = v[i] > m ? v[i] : m;
+    sum += w[i];
+  }
+  const int64_t total = block_sum<int64_t>(sum, tmp);
   red[threadIdx.x] = m;
   __syncthreads();
   for (int off = kBlock / 2; off > 0; off >>= 1) {
@@ -376,43 +409,24 @@ __global__ __launch_bounds__(kBlock) void k_max_reduce(const int32_t *v, int64_t
       red[threadIdx.x] = red[threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *out = red[0];
+  if (threadIdx.x == 0) {
+    out[0] = red[0];
+    out[1] = total;
+  }
 }
 
 // ---------------------------------------------------------------------------
-// 2b. labels of the virtual rows: row N + v for the v-th star net in
-//     ascending order of (median cell, net id), the median being the
-//     distinct cell at index M/2 of the net's ascending list.  Neighbouring
-//     virtual rows then gather from neighbouring cells, and a filter pass's
-//     tiles of virtual rows read a few lines of the signal instead of lines
-//     from all over it.  Star nets are bucketed by median (2^kStarShift
-//     cells per bucket) and every bucket is sorted by one block.
+// 2b. labels of the virtual rows (see step 2)
 // ---------------------------------------------------------------------------
-constexpr int kStarShift = 12;
-constexpr int kStarScatterBlocks = 256;
-
-// skey[s] = (median << 32 | e) for the s-th star net e in net order; counts
-// per bucket.
-__global__ void k_star_keys(const int32_t *is_star, const int64_t *vscan,
-                            const int64_t *net_ptr, const int32_t *M, const int32_t *ucell,
-                            int64_t E, uint64_t *skey, int32_t *bcnt) {
+// The star nets' keys into their buckets' ranges (in any order within a
+// bucket).
+__global__ void k_star_scatter(const int32_t *is_star, const uint64_t *skey, int64_t E,
+                               const int64_t *boff, int32_t *bfill, uint64_t *bkey) {
   const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (e >= E || !is_star[e]) return;
-  const int32_t med = ucell[net_ptr[e] + M[e] / 2];
-  skey[virtual_rank(vscan, e)] = (static_cast<uint64_t>(med) << 32) | static_cast<uint32_t>(e);
-  atomicAdd(bcnt + (med >> kStarShift), 1);
-}
-
-// The keys into their buckets' ranges (in any order within a bucket).
-__global__ void k_star_scatter(const uint64_t *skey, const int64_t *vscan, int64_t E,
-                               const int64_t *boff, int32_t *bfill, uint64_t *bkey) {
-  const int64_t V = virtual_rank(vscan, E);
-  for (int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; s < V;
-       s += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const uint64_t k = skey[s];
-    const int64_t b = static_cast<int64_t>(k >> (32 + kStarShift));
-    bkey[boff[b] + atomicAdd(bfill + b, 1)] = k;
-  }
+  const uint64_t k = skey[e];
+  const int64_t b = static_cast<int64_t>(k >> (32 + kStarShift));
+  bkey[boff[b] + atomicAdd(bfill + b, 1)] = k;
 }
 
 // Block b sorts bucket b (keys are distinct, so the order is unique) and
@@ -1055,18 +1069,17 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
                      (long long)(N + E));
 
   // one zeroed block: the error flags (the low word of a 64-bit word, read
-  // back as int64), the largest net size, the row counts (N + 1 int32) and
-  // the star buckets' counts and fill levels (NB int32 each)
+  // back as int64), the row counts (N + 1 int32) and the star buckets'
+  // counts and fill levels (NB int32 each)
   const int64_t NB = (N >> kStarShift) + 1;
   int64_t *zero_blk = nullptr;
-  const int64_t zero_words = 2 + (N + 2) / 2 + NB;
-  GIFT_TRY(sc.get(&zero_blk, zero_words, "flags, largest net, row counts, star buckets"));
+  const int64_t zero_words = 1 + (N + 2) / 2 + NB;
+  GIFT_TRY(sc.get(&zero_blk, zero_words, "flags, row counts, star buckets"));
   GIFT_HIP(hipMemsetAsync(zero_blk, 0, zero_words * 8, st));
   int64_t *flag64 = zero_blk;
   uint32_t *flag = reinterpret_cast<uint32_t *>(flag64);
-  int64_t *mmax = zero_blk + 1;
-  int32_t *cnt = reinterpret_cast<int32_t *>(zero_blk + 2);
-  int32_t *bcnt = reinterpret_cast<int32_t *>(zero_blk + 2 + (N + 2) / 2);
+  int32_t *cnt = reinterpret_cast<int32_t *>(zero_blk + 1);
+  int32_t *bcnt = reinterpret_cast<int32_t *>(zero_blk + 1 + (N + 2) / 2);
   int32_t *bfill = bcnt + NB;
 
   // 0. check net_ptr and tile the nets, then read the flag, the pin count
@@ -1140,36 +1153,34 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
 
   // 2. classify
   int32_t *is_star = nullptr, *virt_net = nullptr;
-  int64_t *star_code = nullptr, *vscan = nullptr;
   double *wnet = nullptr;
   GIFT_TRY(sc.get(&is_star, E, "star flags"));
-  GIFT_TRY(sc.get(&star_code, E, "star codes"));
-  GIFT_TRY(sc.get(&vscan, E + 1, "virtual ranks and star entry offsets"));
   GIFT_TRY(sc.get(&wnet, E, "net weights"));
   GIFT_TRY(sc.get(&virt_net, E, "virtual nets"));
   int32_t *bmax = nullptr;
+  int64_t *bstar = nullptr, *totals = nullptr;
+  uint64_t *skey = nullptr;
   GIFT_TRY(sc.get(&bmax, grid_for(E), "largest net per block"));
+  GIFT_TRY(sc.get(&bstar, grid_for(E), "star entries per block"));
+  GIFT_TRY(sc.get(&totals, 2, "largest net, star entries"));
+  GIFT_TRY(sc.get(&skey, E, "star keys by net"));
   k_classify<<<grid_for(E), kBlock, 0, st>>>(M, E, d->star_threshold, d->weight_model, is_star,
-                                             wnet, star_code, bmax);
+                                             wnet, bmax, bstar,
+                                             StarKeys{net_ptr, ucell, skey, bcnt});
   GIFT_TRY(check_launch("k_classify"));
-  k_max_reduce<<<1, kBlock, 0, st>>>(bmax, grid_for(E), mmax);
+  k_max_reduce<<<1, kBlock, 0, st>>>(bmax, bstar, grid_for(E), totals);
   GIFT_TRY(check_launch("k_max_reduce"));
-  GIFT_TRY(scan_i64(star_code, vscan, E, st));
 
-  // 2b. virtual row labels (the star codes are consumed by the scan: their
-  //     block holds the keys)
+  // 2b. virtual row labels
   int32_t *vrow = nullptr;
   int64_t *boff = nullptr;
   uint64_t *bkey = nullptr, *btmp = nullptr;
-  uint64_t *skey = reinterpret_cast<uint64_t *>(star_code);
   GIFT_TRY(sc.get(&vrow, E, "virtual row of each star net"));
   GIFT_TRY(sc.get(&boff, NB + 1, "star bucket offsets"));
   GIFT_TRY(sc.get(&bkey, E, "star keys by bucket"));
   GIFT_TRY(sc.get(&btmp, E, "star key sort scratch"));
-  k_star_keys<<<grid_for(E), kBlock, 0, st>>>(is_star, vscan, net_ptr, M, ucell, E, skey, bcnt);
-  GIFT_TRY(check_launch("k_star_keys"));
   GIFT_TRY(scan_i32_to_i64(bcnt, boff, NB, st));
-  k_star_scatter<<<kStarScatterBlocks, kBlock, 0, st>>>(skey, vscan, E, boff, bfill, bkey);
+  k_star_scatter<<<grid_for(E), kBlock, 0, st>>>(is_star, skey, E, boff, bfill, bkey);
   GIFT_TRY(check_launch("k_star_scatter"));
   k_star_sort<<<static_cast<unsigned>(NB), kBlock, 0, st>>>(bkey, btmp, boff, virt_net, vrow);
   GIFT_TRY(check_launch("k_star_sort"));
@@ -1182,15 +1193,15 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
   }
   EmitArgs ea{net_ptr, ucell, pin_net, M, is_star, vrow, E, P, N, KeyLayout{}};
 
-  // sizes back to the host: flag, {V, star entries}, Z, row tiles, largest
-  // net
-  int64_t h1[5] = {0, 0, 0, 0, 0};
+  // sizes back to the host: flag, V (the star nets counted in the median
+  // buckets), Z, row tiles, largest net, star entries
+  int64_t h1[6] = {0, 0, 0, 0, 0, 0};
   {
-    const int64_t *ptrs[5] = {flag64, vscan + E, zoff + N, row_tile_counts, mmax};
-    GIFT_TRY(read_scalars(st, ptrs, 5, h1));
+    const int64_t *ptrs[6] = {flag64, boff + NB, zoff + N, row_tile_counts, totals, totals + 1};
+    GIFT_TRY(read_scalars(st, ptrs, 6, h1));
   }
   if (h1[0] & kFlagBadPin) return set_error(GIFT_EINVAL, "a pin names a cell outside [0, num_cells)");
-  const int64_t V = h1[1] & 0xffffffff, star_entries = h1[1] >> 32;
+  const int64_t V = h1[1], star_entries = h1[5];
   const int64_t Z = h1[2], num_row_tiles = h1[3], R = N + V;
   const KeyLayout L = key_layout(R > 0 ? R - 1 : 0, E > 0 ? E - 1 : 0, h1[4]);
   ea.L = L;
