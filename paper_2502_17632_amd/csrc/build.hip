@@ -1132,7 +1132,9 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
   }
 
   // 2-3. two independent chains: the net classes here, the row offsets and
-  //      row tiles on a side stream, joined before the sizes are read back
+  //      row tiles on a side stream.  The sizes are read back once the
+  //      classes and the row offsets are done; the emit starts then, and the
+  //      row tile count is read back while it runs
   SideGuard side;
   GIFT_TRY(side_stream_acquire(&side.s));
   int32_t *row_tiles = nullptr;
@@ -1146,10 +1148,16 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
   // the event orders the side stream after their earlier users)
   GIFT_TRY(fork_to(st, side.s));
   GIFT_TRY(scan_i32_to_i64(cnt, zoff, N, side.s.stream));
-  // (with a 32-bit copy of the row offsets: the emit's random lookups of
-  // them then touch an 8 MB table instead of 16 MB, more of it in L2)
-  GIFT_TRY(build_tiles64(zoff, N, N, kBuildTiles, side.s.stream, row_tiles, row_tile_counts,
-                         zoff32));
+  // a 32-bit copy of the row offsets: the emit's random lookups of them then
+  // touch an 8 MB table instead of 16 MB, more of it in L2
+  k_row_ptr32<<<grid_for(N + 1), kBlock, 0, side.s.stream>>>(zoff, N, zoff32);
+  GIFT_TRY(check_launch("k_row_ptr32"));
+  // (the main stream waits for this record before it reads the offsets)
+  if (hipEventRecord(side.s.done, side.s.stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return set_error(GIFT_EDEVICE, "side stream ordering failed");
+  }
+  GIFT_TRY(build_tiles64(zoff, N, N, kBuildTiles, side.s.stream, row_tiles, row_tile_counts));
 
   // 2. classify
   int32_t *is_star = nullptr, *virt_net = nullptr;
@@ -1185,25 +1193,24 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
   k_star_sort<<<static_cast<unsigned>(NB), kBlock, 0, st>>>(bkey, btmp, boff, virt_net, vrow);
   GIFT_TRY(check_launch("k_star_sort"));
 
-  // join: this stream waits for the row offsets and row tiles
-  if (hipEventRecord(side.s.done, side.s.stream) != hipSuccess ||
-      hipStreamWaitEvent(st, side.s.done, 0) != hipSuccess) {
+  // this stream waits for the row offsets (the record after their scan)
+  if (hipStreamWaitEvent(st, side.s.done, 0) != hipSuccess) {
     (void)hipGetLastError();
     return set_error(GIFT_EDEVICE, "side stream ordering failed");
   }
   EmitArgs ea{net_ptr, ucell, pin_net, M, is_star, vrow, E, P, N, KeyLayout{}};
 
   // sizes back to the host: flag, V (the star nets counted in the median
-  // buckets), Z, row tiles, largest net, star entries
-  int64_t h1[6] = {0, 0, 0, 0, 0, 0};
+  // buckets), Z, largest net, star entries
+  int64_t h1[5] = {0, 0, 0, 0, 0};
   {
-    const int64_t *ptrs[6] = {flag64, boff + NB, zoff + N, row_tile_counts, totals, totals + 1};
-    GIFT_TRY(read_scalars(st, ptrs, 6, h1));
+    const int64_t *ptrs[5] = {flag64, boff + NB, zoff + N, totals, totals + 1};
+    GIFT_TRY(read_scalars(st, ptrs, 5, h1));
   }
   if (h1[0] & kFlagBadPin) return set_error(GIFT_EINVAL, "a pin names a cell outside [0, num_cells)");
-  const int64_t V = h1[1], star_entries = h1[5];
-  const int64_t Z = h1[2], num_row_tiles = h1[3], R = N + V;
-  const KeyLayout L = key_layout(R > 0 ? R - 1 : 0, E > 0 ? E - 1 : 0, h1[4]);
+  const int64_t V = h1[1], star_entries = h1[4];
+  const int64_t Z = h1[2], R = N + V;
+  const KeyLayout L = key_layout(R > 0 ? R - 1 : 0, E > 0 ? E - 1 : 0, h1[3]);
   ea.L = L;
   if (R >= (int64_t(1) << 31))
     return set_error(GIFT_EUNSUPPORTED, "too many rows (%lld)", (long long)R);
@@ -1221,11 +1228,6 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
   GIFT_TRY(dev_alloc(reinterpret_cast<void **>(&g->deg), R * 8, st, "degrees"));
   g->bytes = (R + 1) * 4 + cap * 12 + R * 8;
 
-  // row tile descriptors (key offsets fit int32: Z <= cap, checked above)
-  TileDesc *row_descs = nullptr;
-  GIFT_TRY(sc.get(&row_descs, num_row_tiles + 1, "row tile descriptors"));
-  GIFT_TRY(tile_descs(row_tiles, zoff, num_row_tiles, st, row_descs));
-
   // 3b. emit
   uint64_t *zkey = nullptr, *zsort = nullptr;
   int32_t *ucnt = nullptr;
@@ -1235,6 +1237,23 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
   // (zoff32 is exact: Z < 2^31 was checked above)
   k_emit<<<grid_for(P), kBlock, 0, st>>>(ea, zoff32, slot, zkey);
   GIFT_TRY(check_launch("k_emit"));
+
+  // the row tile count, read back from the side stream while the emit runs;
+  // then this stream waits for the row tiles
+  int64_t num_row_tiles = 0;
+  {
+    const int64_t *ptrs[1] = {row_tile_counts};
+    GIFT_TRY(read_scalars(side.s.stream, ptrs, 1, &num_row_tiles));
+  }
+  if (hipEventRecord(side.s.done, side.s.stream) != hipSuccess ||
+      hipStreamWaitEvent(st, side.s.done, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return set_error(GIFT_EDEVICE, "side stream ordering failed");
+  }
+  // row tile descriptors (key offsets fit int32: Z <= cap, checked above)
+  TileDesc *row_descs = nullptr;
+  GIFT_TRY(sc.get(&row_descs, num_row_tiles + 1, "row tile descriptors"));
+  GIFT_TRY(tile_descs(row_tiles, zoff, num_row_tiles, st, row_descs));
 
   // 4. sort rows
   if (num_row_tiles > 0) {
