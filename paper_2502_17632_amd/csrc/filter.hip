@@ -492,21 +492,42 @@ __global__ __launch_bounds__(kBlock) void k_prep(LaunchArgs l, int32_t in_dtype,
     double s[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) s[c] = 0.0;
-    // four cells per lane at a time: their columns, then their rows
+    // four cells per lane at a time: their columns, then their rows (held
+    // as float32 when the input is float32, so that wide rows keep the
+    // register count, and the occupancy, of narrow ones); the cells are
+    // added one after another in entry order either way
     int32_t q = p0 + lane;
-    for (; q + 3 * G < p1; q += 4 * G) {
-      int64_t j[4];
+    if (in_dtype == GIFT_F32) {
+      const gptr<const float> xf = to_global(static_cast<const float *>(io.x_in));
+      for (; q + 3 * G < p1; q += 4 * G) {
+        int64_t j[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) j[u] = col_at(q + u * G);
-      double xv[4][C];
+        for (int u = 0; u < 4; ++u) j[u] = col_at(q + u * G);
+        float xv[4][C];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int c = 0; c < C; ++c) xv[u][c] = load_in(io.x_in, in_dtype, j[u] * io.ld_in + col0 + c);
+          for (int c = 0; c < C; ++c) xv[u][c] = xf[j[u] * io.ld_in + col0 + c];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int c = 0; c < C; ++c) s[c] += xv[u][c];
+          for (int c = 0; c < C; ++c) s[c] += static_cast<double>(xv[u][c]);
+      }
+    } else {
+      for (; q + G < p1; q += 2 * G) {
+        int64_t j[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) j[u] = col_at(q + u * G);
+        double xv[2][C];
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+          for (int c = 0; c < C; ++c) xv[u][c] = load_in(io.x_in, in_dtype, j[u] * io.ld_in + col0 + c);
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+          for (int c = 0; c < C; ++c) s[c] += xv[u][c];
+      }
     }
     for (; q < p1; q += G) {
       const int64_t j = col_at(q);
