@@ -131,8 +131,9 @@ __device__ __forceinline__ void emit_row(const FinalArgs &f, const GraphDev &gd,
       for (int c = 0; c < C; ++c) s[c] = 0.0;
       const double dl = cen ? to_global(gd.deg)[lr] : 0.0;
       // every column sums the terms in term order; the saved rows of four
-      // terms are loaded before any of them is added
-      constexpr int kTermBatch = 4;
+      // terms are loaded before any of them is added (one at a time above
+      // four columns, where four would cost occupancy)
+      constexpr int kTermBatch = C <= 4 ? 4 : 1;
       for (int t0 = 0; t0 < f.num_terms; t0 += kTermBatch) {
         double v[kTermBatch][C];
 #pragma unroll
