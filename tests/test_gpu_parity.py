@@ -268,6 +268,27 @@ def test_column_counts_and_leading_dimension(cols):
     assert torch.isnan(out[:, 0]).all() and torch.isnan(out[:, 1 + cols:]).all()
 
 
+@pytest.mark.parametrize("storage,cols", [("f64", 2), ("f64", 8), ("f32", 8)])
+def test_float64_input_with_star_nets(storage, cols):
+    """A float64 signal on a design with star nets: the star rows' start
+    values are gathered from float64 input (two cells per lane at a time),
+    at two and eight columns, stored as float64 or float32."""
+    import torch
+    import paper_2502_17632_amd as gift
+    nl = W.sized(20_000, seed=31)
+    x = np.random.default_rng(31 + cols).normal(500, 20, size=(nl.num_cells, cols))
+    og = O.build_netlist(nl, star_threshold=16, star_order="median")
+    g = gift.build_graph(nl.num_cells, nl.net_ptr, nl.pin_cell, star_threshold=16,
+                         storage=storage, sigmas=[2.0, 4.0])
+    y = gift.filter_placement(g, *PAPER, torch.tensor(x, device="cuda"),
+                              out_dtype=torch.float64)
+    torch.cuda.synchronize()
+    ref = og.filter(x, *PAPER)
+    og.close()
+    g.close()
+    assert_close(y.cpu().numpy(), ref, storage, f"float64 input, {storage}, {cols} columns")
+
+
 def test_fixed_rows_restored():
     nl = W.tiny(seed=2)
     x = W.make_signal(nl, seed=2)
