@@ -457,7 +457,7 @@ __global__ __launch_bounds__(kBlock) void k_prep(LaunchArgs l, int32_t in_dtype,
   // offsets are staged in LDS first, with all of a thread's loads in flight
   // at once (a single row too long for the stage reads them in place); then
   // a group of at least 16 lanes per row, more when the tile has few rows,
-  // gathers the cells' rows four at a time per lane
+  // gathers the cells' rows, several at a time per lane
   constexpr int kPrepCap = TileClass<0>::kCap;
   constexpr int kPrepStage = (kPrepCap + kBlock - 1) / kBlock;
   __shared__ int32_t pcol[kPrepCap];
