@@ -1219,6 +1219,16 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
   const int64_t cap = Z + star_entries;
   if (cap >= (int64_t(1) << 31))
     return set_error(GIFT_EUNSUPPORTED, "too many stored entries (up to %lld)", (long long)cap);
+  // 3b. emit (launched before the host's other allocations, so that the
+  // device starts on it as soon as the sizes are known)
+  uint64_t *zkey = nullptr, *zsort = nullptr;
+  int32_t *ucnt = nullptr;
+  GIFT_TRY(sc.get(&zkey, Z, "emitted keys"));
+  // (zoff32 is exact: Z < 2^31 was checked above)
+  k_emit<<<grid_for(P), kBlock, 0, st>>>(ea, zoff32, slot, zkey);
+  GIFT_TRY(check_launch("k_emit"));
+  GIFT_TRY(sc.get(&zsort, Z, "sorted keys"));
+  GIFT_TRY(sc.get(&ucnt, R, "distinct counts"));
   g->num_cells = N;
   g->num_virtual = V;
   g->num_rows = R;
@@ -1227,16 +1237,6 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
   GIFT_TRY(dev_alloc(reinterpret_cast<void **>(&g->w), cap * 8, st, "weights"));
   GIFT_TRY(dev_alloc(reinterpret_cast<void **>(&g->deg), R * 8, st, "degrees"));
   g->bytes = (R + 1) * 4 + cap * 12 + R * 8;
-
-  // 3b. emit
-  uint64_t *zkey = nullptr, *zsort = nullptr;
-  int32_t *ucnt = nullptr;
-  GIFT_TRY(sc.get(&zkey, Z, "emitted keys"));
-  GIFT_TRY(sc.get(&zsort, Z, "sorted keys"));
-  GIFT_TRY(sc.get(&ucnt, R, "distinct counts"));
-  // (zoff32 is exact: Z < 2^31 was checked above)
-  k_emit<<<grid_for(P), kBlock, 0, st>>>(ea, zoff32, slot, zkey);
-  GIFT_TRY(check_launch("k_emit"));
 
   // the row tile count, read back from the side stream while the emit runs;
   // then this stream waits for the row tiles
