@@ -37,7 +37,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "filter nnz·cols/s + achieved HBM GB/s vs peak; p50/p99 request latency"
-COUNTERS = os.path.join(ROOT, "profiles", "spmm_large_f32_counters.txt")
+# rocprofv3 counter summaries of the SpMM pass, one per storage type
+COUNTERS = os.path.join(ROOT, "profiles", "spmm_large_{storage}_counters.txt")
 STAR = 16
 EQ5 = ([4.0] * 5, [1, 2, 4, 8, 16], [0.2] * 5)
 EQ4 = ([4.0] * 4, [1, 2, 4, 8], [0.25] * 4)
@@ -68,14 +69,14 @@ def host_cpu():
 PROF_EVERY = 5
 
 
-def counter_traffic():
-    """HBM bytes per SpMM launch measured with rocprofv3 counters, if they were
-    taken on the current kernel source."""
+def counter_traffic(storage):
+    """HBM bytes per SpMM launch measured with rocprofv3 counters for this
+    storage type, if they were taken on the current kernel source."""
     src = os.path.join(ROOT, "paper_2502_17632_amd", "csrc", "filter.hip")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     try:
         kv = {}
-        for line in open(COUNTERS):
+        for line in open(COUNTERS.format(storage=storage)):
             if "=" in line and not line.startswith("#"):
                 k, v = line.strip().split("=", 1)
                 kv[k.strip()] = v.strip()
@@ -748,7 +749,7 @@ def main():
     avg_ms = spmm["total_ms"] / max(spmm["launches"], 1)
     bytes_launch = spmm["bytes"] / max(spmm["launches"], 1)
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
-    traffic = counter_traffic()
+    traffic = counter_traffic(args.storage)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "kernel": "k_spmm (non-final pass)",
@@ -867,6 +868,7 @@ def main():
         leg, y_bf16 = filter_leg(gift, W, torch, nl, "bf16", terms, x_host.astype(np.float32),
                                  "large (as above), BF16-stored values and signals, float32 "
                                  "accumulation")
+        leg["spmm_pass_traffic"] = counter_traffic("bf16")
         out["large_bf16"] = leg
         log("[bench] tiny (float64) and medium (float32) workloads")
         out["tiny_f64"] = bench_tiny_latency(gift, W, torch)
