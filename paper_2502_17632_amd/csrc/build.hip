@@ -702,6 +702,9 @@ static_assert((kBTileCap + 1) * 8 + 2 * (kBTileRows + 2) * 4 + (kBTileCap + 1) *
 
 __global__ __launch_bounds__(kBlock) void k_row_merge_tiles(MergeArgs a) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[kMergeSmem];
+  // merged columns of a short-row tile, written out coalesced with the
+  // weights
+  __shared__ int32_t mcol[kBTileCap + 1];
   __shared__ int32_t tmp[kBlock / kWave];
   const TileDesc td = a.tiles[blockIdx.x];
   const int64_t r0 = td.r0, r1 = td.r1, z0 = td.p0, z1 = td.p1;
@@ -804,7 +807,7 @@ __global__ __launch_bounds__(kBlock) void k_row_merge_tiles(MergeArgs a) {
         double s = key_weight(key[i], a);
         for (int j = i + 1; j < end && key_col(key[j], a.L) == c; ++j)
           s = s + key_weight(key[j], a);
-        a.col[o0 + pos] = static_cast<int32_t>(c);
+        mcol[pos] = static_cast<int32_t>(c);
         hw[u] = s;
         hp[u] = pos;
         ++pos;
@@ -816,8 +819,11 @@ __global__ __launch_bounds__(kBlock) void k_row_merge_tiles(MergeArgs a) {
   for (int u = 0; u < kPer; ++u)
     if (hp[u] >= 0) mw[hp[u]] = hw[u];
   __syncthreads();
-  // the weights (two thirds of the bytes written) leave LDS coalesced
-  for (int i = threadIdx.x; i < total; i += kBlock) a.w[o0 + i] = mw[i];
+  // columns and weights leave LDS coalesced
+  for (int i = threadIdx.x; i < total; i += kBlock) {
+    a.col[o0 + i] = mcol[i];
+    a.w[o0 + i] = mw[i];
+  }
   for (int k = threadIdx.x; k < ns; k += kBlock) {
     double d = 0.0;
     for (int i = moff[k]; i < moff[k + 1]; ++i) d = d + mw[i];
@@ -892,8 +898,8 @@ __global__ __launch_bounds__(kBlock) void k_sigma_values(const int32_t *row_ptr,
   __shared__ int32_t loff[TCL::kRows + 2];
   __shared__ uint16_t seg[TCL::kCap + 1];
   __shared__ double ls[TCL::kRows + 1];
-  // each XCD takes a contiguous range of tiles, so the s_j of neighbouring
-  // rows that its tiles share stay in its L2
+  // each XCD takes chunks of consecutive tiles (xcd_remap), so the s_j of
+  // neighbouring rows that its tiles share stay in its L2
   const TileDesc td = tiles[xcd_remap(blockIdx.x, gridDim.x)];
   const int64_t r0 = td.r0, r1 = td.r1, p0 = td.p0, p1 = td.p1;
   const int ns = static_cast<int>(r1 - r0);
