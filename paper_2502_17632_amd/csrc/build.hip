@@ -430,10 +430,12 @@ __global__ void k_star_scatter(const int32_t *is_star, const uint64_t *skey, int
 }
 
 // Block b sorts bucket b (keys are distinct, so the order is unique) and
-// labels its nets: virt_net[v] = e and vrow[e] = v.
+// labels its nets: virt_net[v] = e and vrow[e] = v; the star row N + v has
+// one entry per distinct cell of net e, so its distinct count is M[e].
 __global__ __launch_bounds__(kBlock) void k_star_sort(uint64_t *bkey, uint64_t *btmp,
                                                       const int64_t *boff, int32_t *virt_net,
-                                                      int32_t *vrow) {
+                                                      int32_t *vrow, const int32_t *M,
+                                                      int64_t N, int32_t *ucnt) {
   __shared__ uint64_t lds[kChunk64];
   const int64_t lo = boff[blockIdx.x], n = boff[blockIdx.x + 1] - lo;
   if (n == 0) return;
@@ -444,6 +446,7 @@ __global__ __launch_bounds__(kBlock) void k_star_sort(uint64_t *bkey, uint64_t *
     const int32_t e = static_cast<int32_t>(sorted[i] & 0xffffffffu);
     virt_net[lo + i] = e;
     vrow[e] = static_cast<int32_t>(lo + i);
+    ucnt[N + lo + i] = M[e];
   }
 }
 
@@ -645,16 +648,6 @@ __global__ __launch_bounds__(kBlock) void k_row_sort_tiles(RowArgs a) {
   }
 }
 
-__global__ void k_virtual_counts(const int32_t *virt_net, const int32_t *M, int64_t N,
-                                 int64_t V, int32_t *ucnt) {
-  int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < V) ucnt[N + i] = M[virt_net[i]];
-}
-
-__global__ void k_row_ptr32(const int64_t *rp64, int64_t n, int32_t *rp32) {
-  int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i <= n) rp32[i] = static_cast<int32_t>(rp64[i]);
-}
 
 
 
@@ -1153,11 +1146,9 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
   // (these blocks and cnt were allocated on this stream before the fork, so
   // the event orders the side stream after their earlier users)
   GIFT_TRY(fork_to(st, side.s));
-  GIFT_TRY(scan_i32_to_i64(cnt, zoff, N, side.s.stream));
-  // a 32-bit copy of the row offsets: the emit's random lookups of them then
-  // touch an 8 MB table instead of 16 MB, more of it in L2
-  k_row_ptr32<<<grid_for(N + 1), kBlock, 0, side.s.stream>>>(zoff, N, zoff32);
-  GIFT_TRY(check_launch("k_row_ptr32"));
+  // with a 32-bit copy of the row offsets: the emit's random lookups of them
+  // then touch an 8 MB table instead of 16 MB, more of it in L2
+  GIFT_TRY(scan_i32_to_i64(cnt, zoff, N, side.s.stream, zoff32));
   // (the main stream waits for this record before it reads the offsets)
   if (hipEventRecord(side.s.done, side.s.stream) != hipSuccess) {
     (void)hipGetLastError();
@@ -1193,10 +1184,15 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
   GIFT_TRY(sc.get(&boff, NB + 1, "star bucket offsets"));
   GIFT_TRY(sc.get(&bkey, E, "star keys by bucket"));
   GIFT_TRY(sc.get(&btmp, E, "star key sort scratch"));
+  // distinct columns per row: the star rows' counts come from the star sort,
+  // the cell rows' from the row sort (N + E bounds the rows: V <= E)
+  int32_t *ucnt = nullptr;
+  GIFT_TRY(sc.get(&ucnt, N + E, "distinct counts"));
   GIFT_TRY(scan_i32_to_i64(bcnt, boff, NB, st));
   k_star_scatter<<<grid_for(E), kBlock, 0, st>>>(is_star, skey, E, boff, bfill, bkey);
   GIFT_TRY(check_launch("k_star_scatter"));
-  k_star_sort<<<static_cast<unsigned>(NB), kBlock, 0, st>>>(bkey, btmp, boff, virt_net, vrow);
+  k_star_sort<<<static_cast<unsigned>(NB), kBlock, 0, st>>>(bkey, btmp, boff, virt_net, vrow,
+                                                            M, N, ucnt);
   GIFT_TRY(check_launch("k_star_sort"));
 
   // this stream waits for the row offsets (the record after their scan)
@@ -1228,13 +1224,11 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
   // 3b. emit (launched before the host's other allocations, so that the
   // device starts on it as soon as the sizes are known)
   uint64_t *zkey = nullptr, *zsort = nullptr;
-  int32_t *ucnt = nullptr;
   GIFT_TRY(sc.get(&zkey, Z, "emitted keys"));
   // (zoff32 is exact: Z < 2^31 was checked above)
   k_emit<<<grid_for(P), kBlock, 0, st>>>(ea, zoff32, slot, zkey);
   GIFT_TRY(check_launch("k_emit"));
   GIFT_TRY(sc.get(&zsort, Z, "sorted keys"));
-  GIFT_TRY(sc.get(&ucnt, R, "distinct counts"));
   g->num_cells = N;
   g->num_virtual = V;
   g->num_rows = R;
@@ -1267,18 +1261,12 @@ gift_status build_impl(const gift_graph_desc *d, hipStream_t st, gift_graph *g) 
     k_row_sort_tiles<<<static_cast<unsigned>(num_row_tiles), kBlock, 0, st>>>(ra);
     GIFT_TRY(check_launch("k_row_sort_tiles"));
   }
-  if (V > 0) {
-    k_virtual_counts<<<grid_for(V), kBlock, 0, st>>>(virt_net, M, N, V, ucnt);
-    GIFT_TRY(check_launch("k_virtual_counts"));
-  }
-
   // 5. row_ptr; the SpMM row tiles of every class on a side stream while
   //    this stream merges
   int64_t *rp64 = nullptr;
   GIFT_TRY(sc.get(&rp64, R + 1, "row offsets (64-bit)"));
-  GIFT_TRY(scan_i32_to_i64(ucnt, rp64, R, st));
-  k_row_ptr32<<<grid_for(R + 1), kBlock, 0, st>>>(rp64, R, g->row_ptr);
-  GIFT_TRY(check_launch("k_row_ptr32"));
+  // (the 32-bit row_ptr is exact: the stored entries were bounded below 2^31)
+  GIFT_TRY(scan_i32_to_i64(ucnt, rp64, R, st, g->row_ptr));
   int32_t *tstart[kTileClasses];
   int64_t *tile_counts = nullptr;
   GIFT_TRY(sc.get(&tile_counts, 2 * kTileClasses, "tile counts"));

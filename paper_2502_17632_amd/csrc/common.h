@@ -198,8 +198,10 @@ inline size_t accum_size(int32_t storage) { return storage == GIFT_F64 ? 8 : 4; 
 const SigmaBlock *find_sigma(const gift_graph *g, double sigma);
 gift_status prepare_sigma(gift_graph *g, double sigma, hipStream_t s);
 
-// Exclusive prefix sum: out[0..n] with out[n] = total (int64 output).
-gift_status scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, hipStream_t s);
+// Exclusive prefix sum: out[0..n] with out[n] = total (int64 output); with
+// out32, also a 32-bit copy of out[0..n] (values past 2^31 are not kept).
+gift_status scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, hipStream_t s,
+                            int32_t *out32 = nullptr);
 gift_status scan_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t s);
 
 // Row tiles (see tiles.hip): a tile is a single row longer than long_row or

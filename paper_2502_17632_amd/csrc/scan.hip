@@ -25,14 +25,16 @@ __global__ __launch_bounds__(kBlock) void k_tile_sums(const In *__restrict__ in,
 }
 
 // out[i] = offs[tile] + exclusive prefix within the tile; the last tile also
-// writes out[n] (the grand total).  Each wave scans a contiguous quarter of
-// the tile, 64 consecutive elements per step (coalesced loads and stores),
-// carrying its running sum between steps; the waves' totals are combined
-// once through LDS.
+// writes out[n] (the grand total).  With out32, the same values also go there
+// narrowed to 32 bits (the caller knows that they fit, or never reads the copy
+// otherwise).  Each wave scans a contiguous quarter of the tile, 64
+// consecutive elements per step (coalesced loads and stores), carrying its
+// running sum between steps; the waves' totals are combined once through LDS.
 template <typename In>
 __global__ __launch_bounds__(kBlock) void k_tile_scan(const In *__restrict__ in, int64_t n,
                                                       const int64_t *__restrict__ offs,
-                                                      int64_t *__restrict__ out) {
+                                                      int64_t *__restrict__ out,
+                                                      int32_t *__restrict__ out32) {
   constexpr int kWaves = kBlock / kWave;
   constexpr int64_t kPerWave = kTile / kWaves;
   __shared__ int64_t tmp[kWaves];
@@ -69,16 +71,23 @@ __global__ __launch_bounds__(kBlock) void k_tile_scan(const In *__restrict__ in,
 #pragma unroll
   for (int k = 0; k < kItems; ++k) {
     const int64_t i = wbase + k * kWave + lane;
-    if (i < n) out[i] = off + v[k];
+    if (i < n) {
+      out[i] = off + v[k];
+      if (out32) out32[i] = static_cast<int32_t>(off + v[k]);
+    }
   }
-  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0)
-    out[n] = (offs ? offs[blockIdx.x] : 0) + all;
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+    const int64_t total = (offs ? offs[blockIdx.x] : 0) + all;
+    out[n] = total;
+    if (out32) out32[n] = static_cast<int32_t>(total);
+  }
 }
 
 template <typename In>
-gift_status scan_impl(const In *in, int64_t *out, int64_t n, hipStream_t s) {
+gift_status scan_impl(const In *in, int64_t *out, int64_t n, hipStream_t s,
+                      int32_t *out32 = nullptr) {
   if (n <= kTile) {
-    k_tile_scan<In><<<1, kBlock, 0, s>>>(in, n, nullptr, out);
+    k_tile_scan<In><<<1, kBlock, 0, s>>>(in, n, nullptr, out, out32);
     return check_launch("k_tile_scan");
   }
   int64_t nb = (n + kTile - 1) / kTile;
@@ -89,14 +98,15 @@ gift_status scan_impl(const In *in, int64_t *out, int64_t n, hipStream_t s) {
   k_tile_sums<In><<<static_cast<unsigned>(nb), kBlock, 0, s>>>(in, n, sums);
   GIFT_TRY(check_launch("k_tile_sums"));
   GIFT_TRY(scan_impl<int64_t>(sums, offs, nb, s));
-  k_tile_scan<In><<<static_cast<unsigned>(nb), kBlock, 0, s>>>(in, n, offs, out);
+  k_tile_scan<In><<<static_cast<unsigned>(nb), kBlock, 0, s>>>(in, n, offs, out, out32);
   return check_launch("k_tile_scan");
 }
 
 }  // namespace
 
-gift_status scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, hipStream_t s) {
-  return scan_impl<int32_t>(in, out, n, s);
+gift_status scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, hipStream_t s,
+                            int32_t *out32) {
+  return scan_impl<int32_t>(in, out, n, s, out32);
 }
 
 gift_status scan_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t s) {
