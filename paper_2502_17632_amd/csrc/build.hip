@@ -390,14 +390,32 @@ __global__ __launch_bounds__(kBlock) void k_classify(const int32_t *M, int64_t E
   }
 }
 
-// out[0] = max of v[0..n), out[1] = sum of w[0..n), one block.
+// out[0] = max of v[0..n), out[1] = sum of w[0..n), one block (integers, so
+// the order does not matter).  Each thread has kU loads of each array in
+// flight per step instead of waiting for every load in turn.
 __global__ __launch_bounds__(kBlock) void k_max_reduce(const int32_t *v, const int64_t *w,
                                                        int64_t n, int64_t *out) {
+  constexpr int kU = 8;
   __shared__ int32_t red[kBlock];
   __shared__ int64_t tmp[kBlock / kWave];
   int32_t m = 0;
   int64_t sum = 0;
-  for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+  int64_t i = threadIdx.x;
+  for (; i + (kU - 1) * kBlock < n; i += kU * kBlock) {
+    int32_t vv[kU];
+    int64_t ww[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      vv[u] = v[i + u * kBlock];
+      ww[u] = w[i + u * kBlock];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      m = vv[u] > m ? vv[u] : m;
+      sum += ww[u];
+    }
+  }
+  for (; i < n; i += kBlock) {
     m = v[i] > m ? v[i] : m;
     sum += w[i];
   }
