@@ -230,9 +230,10 @@ gift_status readback_acquire(Readback *r) {
       return GIFT_OK;
     }
   }
-  Readback n{nullptr, nullptr, nullptr, dev};
+  Readback n{nullptr, nullptr, nullptr, dev, 0};
   GIFT_HIP(hipHostMalloc(reinterpret_cast<void **>(&n.host), kReadbackSlots * sizeof(int64_t),
                          hipHostMallocCoherent | hipHostMallocPortable));
+  n.host[kReadbackFlag] = 0;
   hipError_t e = hipHostGetDevicePointer(reinterpret_cast<void **>(&n.dev), n.host, 0);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&n.done, hipEventDisableTiming);
   if (e != hipSuccess) {

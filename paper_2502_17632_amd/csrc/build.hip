@@ -38,6 +38,7 @@
 //   7. per sigma: s_i = 1/sqrt(d_i + sigma), a_ij = (w_ij s_i) s_j,
 //      diag_i = (sigma s_i) s_i
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -1002,35 +1003,50 @@ gift_status prepare_sigma(gift_graph *g, double sigma, hipStream_t st) {
 namespace {
 
 constexpr int kMaxReadback = kReadScalarsMax;
-static_assert(kMaxReadback <= kReadbackSlots, "readback slots");
+static_assert(kMaxReadback <= kReadbackFlag, "readback slots");
 
-// Copies int64 scalars from device memory into one small block so the host
-// reads them with a single transfer.
+// Copies int64 scalars from device memory into the host slot, then writes the
+// ticket that tells the host they are there: every thread's value is made
+// visible to the host (system-scope fence) before the block's barrier, and
+// the ticket is stored after it.
 struct ReadbackPtrs {
   const int64_t *p[kMaxReadback];
 };
-__global__ void k_gather_i64(ReadbackPtrs src, int n, int64_t *dst) {
+__global__ void k_gather_i64(ReadbackPtrs src, int n, int64_t *dst, int64_t ticket) {
   if (threadIdx.x < n) dst[threadIdx.x] = *src.p[threadIdx.x];
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0)
+    __hip_atomic_store(dst + kReadbackFlag, ticket, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 }  // namespace
 
 // Reads `n` device int64 scalars with one launch and one wait: the kernel
-// writes them straight into a pinned host slot.  A slot whose wait failed is
-// not returned to the pool (its kernel may still write it).
+// writes them straight into a pinned host slot, then the slot's next ticket.
+// The host spins on the ticket for a short while (no event to record or
+// query), then falls back to an event wait, which also reports a failed
+// kernel.  A slot whose wait failed is not returned to the pool (its kernel
+// may still write it).
 gift_status read_scalars(hipStream_t st, const int64_t *const *ptrs, int n, int64_t *out) {
   Readback rb{};
   GIFT_TRY(readback_acquire(&rb));
   ReadbackPtrs rp{};
   for (int i = 0; i < n; ++i) rp.p[i] = ptrs[i];
-  k_gather_i64<<<1, 64, 0, st>>>(rp, n, rb.dev);
+  const int64_t ticket = ++rb.ticket;
+  k_gather_i64<<<1, 64, 0, st>>>(rp, n, rb.dev, ticket);
   gift_status s = check_launch("k_gather_i64");
   if (s != GIFT_OK) {
     readback_release(rb);
     return s;
   }
-  GIFT_TRY(readback_wait(rb, st));
   const volatile int64_t *h = rb.host;
+  bool seen = false;
+  const auto t0 = std::chrono::steady_clock::now();
+  while (!(seen = h[kReadbackFlag] == ticket) &&
+         std::chrono::steady_clock::now() - t0 < std::chrono::microseconds(300)) {
+  }
+  if (!seen) GIFT_TRY(readback_wait(rb, st));
   for (int i = 0; i < n; ++i) out[i] = h[i];
   readback_release(rb);
   return GIFT_OK;

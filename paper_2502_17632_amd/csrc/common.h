@@ -87,13 +87,16 @@ void pool_stats(int64_t *held, int64_t *in_use);
 // kReadbackSlots int64 values in pinned, host-coherent memory that a kernel
 // writes directly, and an event recorded after that kernel.  Slots come from
 // a per-device pool (allocated once, kept for the life of the process) and
-// are returned with readback_release.
+// are returned with readback_release.  A kernel may also announce its values
+// by writing the slot's next ticket into value kReadbackFlag after them.
 constexpr int kReadbackSlots = 16;
+constexpr int kReadbackFlag = kReadbackSlots - 1;
 struct Readback {
   int64_t *host;  // kReadbackSlots values, read by the host
   int64_t *dev;   // the same memory as device code addresses it
   hipEvent_t done;
   int device;
+  int64_t ticket;  // the last ticket used with this slot (0: none)
 };
 gift_status readback_acquire(Readback *r);
 void readback_release(const Readback &r);
